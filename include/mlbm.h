@@ -1,0 +1,213 @@
+/*
+ * mlbm.h -- C ABI of the MI355X (gfx950) lattice Boltzmann library for
+ * generalized metrics (Debus, Mendoza & Herrmann, "Dean Instability in
+ * Double-Curved Channels", arXiv:1411.3133).
+ *
+ * One time step is the update of Sec. II, Eq. (3): pull streaming in
+ * coordinate space with bounce-back walls and periodic axes, moments
+ * (Sec. II, rho' = sum f, rho' u = sum c f), the metric Hermite equilibrium
+ * through third order (Eq. (6) and the lattice f^eq that follows it), the
+ * stress-corrected forcing with F_lambda^i = -Gamma^i_jk c^j c^k + F_ext^i
+ * (the discrete forcing term after Eq. (7)), and BGK relaxation.
+ *
+ * Conventions used by every call:
+ *  - Status codes are returned; no C++ exception crosses this boundary.
+ *    mlbm_last_error() returns a thread-local message for the last failure.
+ *  - The library owns every device allocation behind a handle.  Host
+ *    pointers passed in are read (or written) during the call only and stay
+ *    owned by the caller.
+ *  - Node order is [x1][x2][x3] with x3 fastest: x1 = r (or x), x2 = theta
+ *    (streamwise), x3 = z (cylinder) or phi (ellipsoid).  N = n1 n2 n3.
+ *  - Velocity index lambda follows Table I: rest, (+-1,0,0), (0,+-1,0),
+ *    (0,0,+-1), (+-1,+-1,0), (+-1,0,+-1), (0,+-1,+-1), (+-1,+-1,+-1),
+ *    (+-3,0,0), (0,+-3,0), (0,0,+-3), (+-3,+-3,+-3); inside a group the
+ *    signs run with "+" first and the last component fastest.
+ *  - Velocities crossing the boundary are physical contravariant components
+ *    u^i = dx^i/dt, laid out [3][N].  Densities are rho = rho' sqrt(g) (Sec. II).
+ *  - A handle is bound to one HIP stream and is not thread safe.
+ */
+#ifndef MLBM_H
+#define MLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MLBM_OK = 0,
+    MLBM_E_ARG = 1,       /* invalid argument                                   */
+    MLBM_E_HIP = 2,       /* a HIP runtime call failed                          */
+    MLBM_E_OOM = 3,       /* device allocation failed                           */
+    MLBM_E_UNSTABLE = 4,  /* a stationarity check found NaN, rho' <= 0 or |u| > 1 */
+    MLBM_E_STATE = 5,     /* call not valid in the current state                */
+    MLBM_E_IO = 6         /* checkpoint file could not be read or written       */
+} mlbm_status;
+
+typedef enum {
+    MLBM_FLAT = 0,        /* Cartesian, g = delta, Gamma = 0                       */
+    MLBM_CYLINDER = 1,    /* (r, theta, z), Sec. III                               */
+    MLBM_ELLIPSOID = 2    /* (r, theta, phi) with a = c = 1, Sec. IV, at theta = 0  */
+} mlbm_kind;
+
+typedef enum {
+    MLBM_F64 = 0,         /* populations stored and collided in FP64              */
+    MLBM_F32 = 1,         /* stored and collided in FP32                          */
+    MLBM_F16 = 2,         /* stored as FP16 offsets f/w - 1, collided in FP32      */
+    MLBM_BF16 = 3         /* stored as BF16 offsets f/w - 1, collided in FP32      */
+} mlbm_precision;
+
+enum { MLBM_WALL_AXIS1 = 1, MLBM_WALL_AXIS3 = 4 };
+enum { MLBM_FORCING_IMPROVED = 0, MLBM_FORCING_OLD = 1 };
+
+/* Problem description, following the paper's statement of the problem
+ * (Sec. III and Sec. IV): coordinate system and curvature, grid, tau,
+ * driving force, walls, initial velocity.
+ *  kind          mlbm_kind.
+ *  n1, n2, n3    nodes along r, theta, z/phi; each >= 1, an axis with walls
+ *                needs >= 4 nodes.
+ *  walls         bit mask of MLBM_WALL_AXIS1 / MLBM_WALL_AXIS3; axes without
+ *                walls (and axis 2 always) are periodic.  Walls are halfway:
+ *                half a spacing outside the first and last node.
+ *  forcing_mode  MLBM_FORCING_IMPROVED (a2 = a2_eq - sigma) or MLBM_FORCING_OLD.
+ *  precision     mlbm_precision.
+ *  check_every   K, steps per stationarity window (even, >= 2); 0 means 100.
+ *  r_inner       inner radius r_i (ignored for MLBM_FLAT).
+ *  width         channel width d = r_o - r_i; Dt = Dr = d / n1.
+ *  b             ellipsoid semi-axis b (streamwise curvature radius r_i b^2).
+ *  tau           BGK relaxation parameter, > 0.5.
+ *  force         covariant streamwise body force K (physical units); the
+ *                contravariant force is g^{i theta} K.
+ *  init_u        NULL for rest, else 3 N doubles [3][N] (host, copied). */
+typedef struct {
+    int32_t kind;
+    int32_t n1, n2, n3;
+    int32_t walls;
+    int32_t forcing_mode;
+    int32_t precision;
+    int32_t check_every;
+    double r_inner;
+    double width;
+    double b;
+    double tau;
+    double force;
+    const double *init_u;
+} mlbm_desc;
+
+typedef struct mlbm_sim_s *mlbm_handle;
+typedef struct mlbm_batch_s *mlbm_batch;
+
+/* Create a single-instance simulation: validates `d`, computes the FP64
+ * lattice geometry (metric, inverse, sqrt(g), Christoffels, unit force) on
+ * the device, allocates populations and sets f* = f_eq(rho' = 1/sqrt(g), u)
+ * (rho = 1 at t = 0, Sec. IV A).  `hip_stream` is a hipStream_t or NULL for
+ * a stream the handle creates.  Errors: E_ARG, E_OOM, E_HIP. */
+mlbm_status mlbm_init_geometry(const mlbm_desc *d, void *hip_stream, mlbm_handle *out);
+
+/* Enqueue n time steps of Eq. (3) on the handle's stream and return without
+ * waiting.  Every K-th step (counted from t = 0) also records the lattice
+ * velocity and reduces the stationarity residual and the instability flag.
+ * Errors: E_ARG (n < 0), E_HIP. */
+mlbm_status mlbm_step(mlbm_handle h, int64_t n);
+
+/* Moments of the current state as seen by the next collision: rho = rho'
+ * sqrt(g) (N doubles) and physical contravariant u (3 N doubles, [3][N]).
+ * Either pointer may be NULL.  on_device = 0: host buffers; 1: device
+ * buffers.  Waits for the stream. */
+mlbm_status mlbm_moments(mlbm_handle h, double *rho, double *u, int on_device);
+
+/* Observables of Sec. III and Sec. IV from the current moments:
+ * mean absolute streamwise vorticity <omega^theta> (Sec. III / Sec. IV
+ * formulas, derivatives by second-order differences, one-sided next to
+ * walls), mean streamwise velocity <v_theta> and the measured Dean number
+ * De = <v_theta> d / nu sqrt(d / R) (Eq. (8)).  Averaged over theta slabs.
+ * Waits for the stream. */
+mlbm_status mlbm_vortex_intensity(mlbm_handle h, double *omega_mean, double *v_mean, double *De);
+
+/* Residual of the last completed window: ||U_w - U_{w-1}|| / ||U_w|| over all
+ * nodes and components (lattice units); -1 before two windows completed.
+ * *bad receives the sticky instability flag.  Waits for the stream. */
+mlbm_status mlbm_residual(mlbm_handle h, double *r, int *bad);
+
+/* Advance whole windows until the residual is <= tol or max_steps are done.
+ * Returns E_UNSTABLE when the flag trips. */
+mlbm_status mlbm_run_until(mlbm_handle h, double tol, int64_t max_steps, int64_t *steps_taken);
+
+/* Decoded populations f (absolute, FP64) of the current state, [41][N], host. */
+mlbm_status mlbm_get_populations(mlbm_handle h, double *f);
+/* Overwrite the current state (encoded into the storage precision). */
+mlbm_status mlbm_set_populations(mlbm_handle h, const double *f);
+
+/* One step of the nodes listed, from the current state, without advancing:
+ * out[k][41] = f* at node nodes[k] (host arrays).  Waits for the stream. */
+mlbm_status mlbm_step_nodes(mlbm_handle h, const int64_t *nodes, int64_t count, double *out);
+
+/* Pull map of the streaming step with walls, evaluated on the host with the
+ * same fold the kernels use: for node n and velocity q the population is
+ * read from node src_node[n*41 + q], velocity src_q[n*41 + q].  Caller-owned
+ * host arrays of 41 N entries.  Needs no GPU.  Errors: E_ARG. */
+mlbm_status mlbm_pull_map(const mlbm_desc *d, int64_t *src_node, int32_t *src_q);
+
+/* Number of completed steps. */
+int64_t mlbm_time(mlbm_handle h);
+
+/* Checkpoint: raw storage-precision populations, step counter and the
+ * description; resume is bitwise identical.  Errors: E_IO. */
+mlbm_status mlbm_save(mlbm_handle h, const char *path);
+mlbm_status mlbm_load(const char *path, void *hip_stream, mlbm_handle *out);
+
+/* Free the handle and its device memory (NULL is ignored). */
+void mlbm_destroy(mlbm_handle h);
+
+/* Thread-local text of the last error. */
+const char *mlbm_last_error(void);
+
+/* The library's D3Q41 table (Table I): c[41][3], w[41], c_s^2.  Returns 41. */
+int mlbm_lattice(int32_t *c, double *w, double *cs2);
+
+/* ---------------- batched persistent engine ---------------------------- */
+
+/* Many instances advanced by one launch per step over a flat tile queue.
+ * Every description must share `precision` and `check_every`; kinds,
+ * sizes, tau, force and walls may differ.  Errors: E_ARG, E_OOM, E_HIP. */
+mlbm_status mlbm_batch_create(const mlbm_desc *ds, int n, void *hip_stream, mlbm_batch *out);
+
+/* Enqueue n steps of every active instance (asynchronous). */
+mlbm_status mlbm_batch_step(mlbm_batch b, int64_t n);
+
+/* Advance whole windows; an instance retires when its residual is <= tol,
+ * when it becomes unstable or after max_steps.  steps[i] receives the steps
+ * instance i took, residual[i] its last residual, status[i] 0 converged,
+ * 1 hit max_steps, 2 unstable (each array may be NULL). */
+mlbm_status mlbm_batch_run_until(mlbm_batch b, double tol, int64_t max_steps, int64_t *steps,
+                                 double *residual, int32_t *status);
+
+/* Non-owning view of instance i, valid until the batch is destroyed; every
+ * single-instance query above (moments, vortex_intensity, residual,
+ * get/set_populations, step_nodes, time) accepts it.  mlbm_step and
+ * mlbm_destroy on a view return E_STATE / do nothing. */
+mlbm_status mlbm_batch_get(mlbm_batch b, int i, mlbm_handle *view);
+
+/* Launch shape: workgroup size (64, 128, 256, 512) and persistent grid
+ * (0 = one workgroup per tile).  mlbm_batch_autotune times the candidate
+ * shapes on the batch itself (hipEvents, `steps` steps each, state restored
+ * afterwards) and keeps the fastest; best_block/best_grid may be NULL. */
+mlbm_status mlbm_batch_set_launch(mlbm_batch b, int block, int grid);
+mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *best_grid);
+
+/* Capture K-step windows in a hipGraph (1, default) or launch eagerly (0). */
+mlbm_status mlbm_batch_use_graph(mlbm_batch b, int on);
+
+/* Mean device time per step of the step kernel measured with hipEvents on
+ * the batch stream over the last mlbm_batch_step call (ms), -1 if none. */
+double mlbm_batch_last_step_ms(mlbm_batch b);
+
+int mlbm_batch_size(mlbm_batch b);
+void mlbm_batch_destroy(mlbm_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLBM_H */

@@ -1,0 +1,396 @@
+// Auxiliary device kernels: geometry precompute (FP64), initial state,
+// window reductions, moments, observables, storage codecs and a sampled
+// one-step update.
+#include "core.hpp"
+#include "kernels.hpp"
+
+namespace mlbm {
+
+// ------------------------------------------------------------------------
+// Geometry (Sec. III cylinder, Sec. IV ellipsoid at theta = 0), FP64.
+// Physical metric g_ij (diagonal for every supported kind at theta = 0),
+// printed Christoffel symbols, lattice scaling with s_i = Dx^i / Dt:
+//   lattice g^ij = g^ij / (s_i s_j), Gamma_lat^i_jk = Dt Gamma^i_jk s_j s_k / s_i,
+//   unit force F^i = Dt g^{i theta} / s_i (times the covariant K at run time).
+// ------------------------------------------------------------------------
+
+__global__ void geometry_kernel(double *geo, GeoParams p)
+{
+    const int NX = p.n1 * p.n3g;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= NX) return;
+    const int x1 = idx / p.n3g, x3 = idx - x1 * p.n3g;
+    const double dt = p.dt;
+    double X1, X3;
+    double g11 = 1.0, g22 = 1.0, g33 = 1.0;
+    double G[3][3][3] = {};
+    if (p.kind == 0) {                        // flat
+        X1 = (x1 + 0.5) * dt * p.s[0];
+        X3 = (x3 + 0.5) * dt * p.s[2];
+    } else if (p.kind == 1) {                 // cylinder (r, theta, z)
+        const double r = p.r_inner + (x1 + 0.5) * dt * p.s[0];
+        X1 = r;
+        X3 = (x3 + 0.5) * dt * p.s[2];
+        g22 = r * r;
+        G[0][1][1] = -r;                      // Gamma^r_{theta theta}
+        G[1][0][1] = G[1][1][0] = 1.0 / r;    // Gamma^theta_{r theta}
+    } else {                                  // ellipsoid (r, theta, phi), a = c = 1, theta = 0
+        const double r = p.r_inner + (x1 + 0.5) * dt * p.s[0];
+        const double ph = (x3 + 0.5 - 0.5 * p.n3) * dt * p.s[2];
+        const double cp = cos(ph), sp = sin(ph);
+        X1 = r;
+        X3 = ph;
+        g22 = r * r * p.b * p.b * cp * cp;
+        g33 = r * r;
+        G[0][1][1] = -r * cp * cp;                    // Gamma^r_{theta theta}
+        G[0][2][2] = -r;                              // Gamma^r_{phi phi}
+        G[1][0][1] = G[1][1][0] = 1.0 / r;            // Gamma^theta_{r theta}
+        G[2][0][2] = G[2][2][0] = 1.0 / r;            // Gamma^phi_{r phi}
+        G[1][1][2] = G[1][2][1] = -sp / cp;           // Gamma^theta_{theta phi}
+        G[2][1][1] = sp * cp;                         // Gamma^phi_{theta theta}
+    }
+    const double *s = p.s;
+    const double gi[3] = {1.0 / g11, 1.0 / g22, 1.0 / g33};
+    double *o = geo + idx;
+    auto put = [&](int field, double v) { o[(size_t)field * NX] = v; };
+    put(G_D11, gi[0] / (s[0] * s[0]) - 1.0);
+    put(G_D22, gi[1] / (s[1] * s[1]) - 1.0);
+    put(G_D33, gi[2] / (s[2] * s[2]) - 1.0);
+    put(G_D12, 0.0); put(G_D13, 0.0); put(G_D23, 0.0);
+    for (int i = 0; i < 3; ++i) {
+        const int jk[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+        for (int e = 0; e < 6; ++e) {
+            const int j = jk[e][0], k = jk[e][1];
+            put(G_1_11 + 6 * i + e, dt * G[i][j][k] * s[j] * s[k] / s[i]);
+        }
+    }
+    put(G_F1, 0.0);
+    put(G_F2, dt * gi[1] / s[1]);
+    put(G_F3, 0.0);
+    put(G_SQRTG, sqrt(g11 * g22 * g33) * s[0] * s[1] * s[2]);
+    put(G_X1, X1);
+    put(G_X3, X3);
+}
+
+hipError_t launch_geometry(double *geo, const GeoParams &p, hipStream_t s)
+{
+    const int NX = p.n1 * p.n3g;
+    hipLaunchKernelGGL(geometry_kernel, dim3((NX + 255) / 256), dim3(256), 0, s, geo, p);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Initial state f* = f_eq(rho', U) with rho' = 1/sqrt(g) (rho = 1), in FP64
+// ------------------------------------------------------------------------
+
+template <int ST>
+__global__ void init_kernel(const InstDesc *dd, const double *init_u, int parity)
+{
+    const InstDesc &d = *dd;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= d.N) return;
+    const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
+    (void)x2;
+    const int NX = d.n1 * d.n3g;
+    const int gi = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
+    const double *geo = d.geo;
+    double D[3][3];
+    D[0][0] = geo[G_D11 * NX + gi]; D[1][1] = geo[G_D22 * NX + gi]; D[2][2] = geo[G_D33 * NX + gi];
+    D[0][1] = D[1][0] = geo[G_D12 * NX + gi];
+    D[0][2] = D[2][0] = geo[G_D13 * NX + gi];
+    D[1][2] = D[2][1] = geo[G_D23 * NX + gi];
+    const double rho = 1.0 / geo[G_SQRTG * NX + gi];
+    double U[3] = {0.0, 0.0, 0.0};
+    if (init_u)
+        for (int i = 0; i < 3; ++i) U[i] = init_u[(size_t)i * d.N + n] / d.s[i];
+    const double cs2 = CS2;
+    const double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+    const double trD = D[0][0] + D[1][1] + D[2][2];
+    double DU[3];
+    for (int i = 0; i < 3; ++i) DU[i] = D[i][0] * U[0] + D[i][1] * U[1] + D[i][2] * U[2];
+    using T = typename Codec<ST>::T;
+    T *dst = (T *)d.f[parity];
+    for (int q = 0; q < Q; ++q) {
+        const double c0 = CV[q][0], c1 = CV[q][1], c2 = CV[q][2];
+        const double cu = c0 * U[0] + c1 * U[1] + c2 * U[2];
+        const double cDu = c0 * DU[0] + c1 * DU[1] + c2 * DU[2];
+        double cDc = 0.0;
+        const double c[3] = {c0, c1, c2};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) cDc += c[i] * D[i][j] * c[j];
+        const double Em1 = (cDc - cs2 * trD) / (2.0 * cs2) + (cu * cu - cs2 * uu) / (2.0 * cs2 * cs2);
+        const double Od = cu / cs2 + (cu * cu * cu - 3.0 * cs2 * uu * cu) / (6.0 * cs2 * cs2 * cs2)
+                        + (cDc * cu - cs2 * trD * cu - 2.0 * cs2 * cDu) / (2.0 * cs2 * cs2);
+        const double w = wq(q);
+        const double g = w * ((rho - 1.0) + rho * (Em1 + Od));
+        dst[(size_t)q * d.N + n] = Codec<ST>::from_f64(g, w);
+    }
+}
+
+hipError_t launch_init(const InstDesc *d_desc, const InstDesc &h, int st, const double *init_u, int parity,
+                       hipStream_t s)
+{
+    const dim3 grid((h.N + 255) / 256), block(256);
+    switch (st) {
+    case ST_F64: hipLaunchKernelGGL(init_kernel<ST_F64>, grid, block, 0, s, d_desc, init_u, parity); break;
+    case ST_F32: hipLaunchKernelGGL(init_kernel<ST_F32>, grid, block, 0, s, d_desc, init_u, parity); break;
+    case ST_F16: hipLaunchKernelGGL(init_kernel<ST_F16>, grid, block, 0, s, d_desc, init_u, parity); break;
+    default: hipLaunchKernelGGL(init_kernel<ST_BF16>, grid, block, 0, s, d_desc, init_u, parity); break;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Window reduction: one thread per instance, fixed summation order
+// ------------------------------------------------------------------------
+
+__global__ void reduce_kernel(const double *partials, const int *pb, const int *pc, WindowState *ws, int ninst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || pb[i] < 0) return;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int k = 0; k < pc[i]; ++k) {
+        const double *p = partials + 3 * (size_t)(pb[i] + k);
+        a += p[0]; b += p[1]; c += p[2];
+    }
+    WindowState w = ws[i];
+    w.checks += 1;
+    w.residual = w.checks >= 2 ? sqrt(a) / sqrt(b) : -1.0;
+    if (c > 0.0) w.bad = 1;
+    ws[i] = w;
+}
+
+hipError_t launch_reduce(const double *partials, const int *pb, const int *pc, WindowState *ws, int ninst,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(reduce_kernel, dim3((ninst + 63) / 64), dim3(64), 0, s, partials, pb, pc, ws, ninst);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Moments of the streamed state (FP64)
+// ------------------------------------------------------------------------
+
+template <int ST>
+__device__ __forceinline__ void pull_f64(const InstDesc &d, int parity, int x1, int x2, int x3, double (&g)[Q])
+{
+    using T = typename Codec<ST>::T;
+    const T *src = (const T *)d.f[parity];
+    static_for<0, Q>([&](auto q) {
+        constexpr int qo = opposite(q);
+        bool flip;
+        const int n = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip);
+        const int qs = flip ? qo : (int)q;
+        g[q] = Codec<ST>::to_f64(src[(size_t)qs * d.N + n], wq(q));
+    });
+}
+
+template <int ST>
+__global__ void moments_kernel(const InstDesc *dd, int parity, double *rho, double *u)
+{
+    const InstDesc &d = *dd;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= d.N) return;
+    const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
+    double g[Q];
+    pull_f64<ST>(d, parity, x1, x2, x3, g);
+    double r, U[3];
+    moments_only<double>(g, r, U);
+    const int NX = d.n1 * d.n3g;
+    const int gi = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
+    if (rho) rho[n] = r * d.geo[G_SQRTG * NX + gi];
+    if (u)
+        for (int i = 0; i < 3; ++i) u[(size_t)i * d.N + n] = d.s[i] * U[i];
+}
+
+hipError_t launch_moments(const InstDesc *d_desc, const InstDesc &h, int st, int parity, double *rho, double *u,
+                          hipStream_t s)
+{
+    const dim3 grid((h.N + 255) / 256), block(256);
+    switch (st) {
+    case ST_F64: hipLaunchKernelGGL(moments_kernel<ST_F64>, grid, block, 0, s, d_desc, parity, rho, u); break;
+    case ST_F32: hipLaunchKernelGGL(moments_kernel<ST_F32>, grid, block, 0, s, d_desc, parity, rho, u); break;
+    case ST_F16: hipLaunchKernelGGL(moments_kernel<ST_F16>, grid, block, 0, s, d_desc, parity, rho, u); break;
+    default: hipLaunchKernelGGL(moments_kernel<ST_BF16>, grid, block, 0, s, d_desc, parity, rho, u); break;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Observables (Sec. III, Sec. IV): per-block partial sums of
+//   <v_theta> numerator, <omega> numerator and the area S.
+// Derivatives: second-order central differences, periodic wrap; next to a
+// wall the one-sided second-order formula through u = 0 at the halfway wall.
+// ------------------------------------------------------------------------
+
+__device__ __forceinline__ double ddx_axis(const double *f, int stride, int x, int n, bool walled, double h)
+{
+    if (walled) {
+        if (n == 1) return 0.0;
+        if (x == 0) return (f[0] + f[stride] / 3.0) / h;
+        if (x == n - 1) return -(f[0] + f[-stride] / 3.0) / h;
+        return (f[stride] - f[-stride]) / (2.0 * h);
+    }
+    const int xp = x + 1 == n ? 0 : x + 1, xm = x == 0 ? n - 1 : x - 1;
+    return (f[(xp - x) * stride] - f[(xm - x) * stride]) / (2.0 * h);
+}
+
+__global__ void vortex_kernel(InstDesc d, int kind, double b, double h1, double h3, const double *u,
+                              double *partials)
+{
+    __shared__ double red[4][3];
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double vs = 0.0, os = 0.0, as = 0.0;
+    if (n < d.N) {
+        const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
+        (void)x2;
+        const int NX = d.n1 * d.n3g;
+        const int gi = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
+        const double r = d.geo[G_X1 * NX + gi], ph = d.geo[G_X3 * NX + gi];
+        const double *ur = u + n, *uz = u + 2 * (size_t)d.N + n;
+        const double d3ur = ddx_axis(ur, 1, x3, d.n3, (d.walls & 4) != 0, h3);
+        const double d1uz = ddx_axis(uz, d.P, x1, d.n1, (d.walls & 1) != 0, h1);
+        const double vort = fabs(d3ur - d1uz);
+        const double uth = u[(size_t)d.N + n];
+        double wv = 1.0, wo = 1.0, ws = 1.0;
+        if (kind == 1) { wv = r; wo = r; }
+        else if (kind == 2) { const double cp = cos(ph); wv = r * r * b * cp; wo = r * b * cp; ws = r; }
+        vs = uth * wv * h1 * h3;
+        os = vort * wo * h1 * h3;
+        as = ws * h1 * h3;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        vs += __shfl_xor(vs, off, 64);
+        os += __shfl_xor(os, off, 64);
+        as += __shfl_xor(as, off, 64);
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) { red[wave][0] = vs; red[wave][1] = os; red[wave][2] = as; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, c = 0.0, e = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += red[w][0]; c += red[w][1]; e += red[w][2]; }
+        partials[3 * blockIdx.x + 0] = a;
+        partials[3 * blockIdx.x + 1] = c;
+        partials[3 * blockIdx.x + 2] = e;
+    }
+}
+
+hipError_t launch_vortex(const InstDesc &h, int kind, double b, double h1, double h3, const double *u,
+                         double *partials, int *nblocks, hipStream_t s)
+{
+    const int nb = (h.N + 255) / 256;
+    *nblocks = nb;
+    hipLaunchKernelGGL(vortex_kernel, dim3(nb), dim3(256), 0, s, h, kind, b, h1, h3, u, partials);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Codecs: stored offsets <-> absolute FP64 populations, layout [41][N]
+// ------------------------------------------------------------------------
+
+template <int ST>
+__global__ void decode_kernel(InstDesc d, int parity, double *f)
+{
+    using T = typename Codec<ST>::T;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)Q * d.N) return;
+    const int q = (int)(i / d.N);
+    const double w = wq(q);
+    f[i] = Codec<ST>::to_f64(((const T *)d.f[parity])[i], w) + w;
+}
+
+template <int ST>
+__global__ void encode_kernel(InstDesc d, int parity, const double *f)
+{
+    using T = typename Codec<ST>::T;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)Q * d.N) return;
+    const int q = (int)(i / d.N);
+    const double w = wq(q);
+    ((T *)d.f[parity])[i] = Codec<ST>::from_f64(f[i] - w, w);
+}
+
+hipError_t launch_decode(const InstDesc &h, int st, int parity, double *f, hipStream_t s)
+{
+    const size_t tot = (size_t)Q * h.N;
+    const dim3 grid((unsigned)((tot + 255) / 256)), block(256);
+    switch (st) {
+    case ST_F64: hipLaunchKernelGGL(decode_kernel<ST_F64>, grid, block, 0, s, h, parity, f); break;
+    case ST_F32: hipLaunchKernelGGL(decode_kernel<ST_F32>, grid, block, 0, s, h, parity, f); break;
+    case ST_F16: hipLaunchKernelGGL(decode_kernel<ST_F16>, grid, block, 0, s, h, parity, f); break;
+    default: hipLaunchKernelGGL(decode_kernel<ST_BF16>, grid, block, 0, s, h, parity, f); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_encode(const InstDesc &h, int st, int parity, const double *f, hipStream_t s)
+{
+    const size_t tot = (size_t)Q * h.N;
+    const dim3 grid((unsigned)((tot + 255) / 256)), block(256);
+    switch (st) {
+    case ST_F64: hipLaunchKernelGGL(encode_kernel<ST_F64>, grid, block, 0, s, h, parity, f); break;
+    case ST_F32: hipLaunchKernelGGL(encode_kernel<ST_F32>, grid, block, 0, s, h, parity, f); break;
+    case ST_F16: hipLaunchKernelGGL(encode_kernel<ST_F16>, grid, block, 0, s, h, parity, f); break;
+    default: hipLaunchKernelGGL(encode_kernel<ST_BF16>, grid, block, 0, s, h, parity, f); break;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// One update of listed nodes from the current state (same gather and
+// collision as the step kernel, in the step kernel's compute precision)
+// ------------------------------------------------------------------------
+
+template <int PAT, int ST>
+__global__ void step_nodes_kernel(const InstDesc *dd, int parity, const int64_t *nodes, int64_t count, double *out)
+{
+    using T = typename Codec<ST>::T;
+    using C = typename Codec<ST>::C;
+    const InstDesc &d = *dd;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count) return;
+    const int n = (int)nodes[k];
+    if (n < 0 || n >= d.N) return;
+    const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
+    C g[Q];
+    gather_general<ST>((const T *)d.f[parity], d, x1, x2, x3, g);
+    NodeGeo<PAT, C> geo;
+    geo.load(d.geo, x1 * d.n3g + (d.n3g > 1 ? x3 : 0), d.n1 * d.n3g, (C)d.force);
+    C rho, u[3];
+    collide<PAT, C>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
+    static_for<0, Q>([&](auto q) {
+        // round through the storage format, as the step kernel stores it
+        T tmp;
+        Codec<ST>::store(&tmp, g[q], (C)(1.0 / wq(q)));
+        out[k * Q + q] = Codec<ST>::to_f64(tmp, wq(q)) + wq(q);
+    });
+}
+
+template <int PAT>
+static void launch_sn_pat(const InstDesc *dd, int st, int parity, const int64_t *nodes, int64_t count, double *out,
+                          hipStream_t s)
+{
+    const dim3 grid((unsigned)((count + 63) / 64)), block(64);
+    switch (st) {
+    case ST_F64: hipLaunchKernelGGL((step_nodes_kernel<PAT, ST_F64>), grid, block, 0, s, dd, parity, nodes, count, out); break;
+    case ST_F32: hipLaunchKernelGGL((step_nodes_kernel<PAT, ST_F32>), grid, block, 0, s, dd, parity, nodes, count, out); break;
+    case ST_F16: hipLaunchKernelGGL((step_nodes_kernel<PAT, ST_F16>), grid, block, 0, s, dd, parity, nodes, count, out); break;
+    default: hipLaunchKernelGGL((step_nodes_kernel<PAT, ST_BF16>), grid, block, 0, s, dd, parity, nodes, count, out); break;
+    }
+}
+
+hipError_t launch_step_nodes(const InstDesc *d_desc, const InstDesc &h, int pat, int st, int parity,
+                             const int64_t *nodes, int64_t count, double *out, hipStream_t s)
+{
+    (void)h;
+    if (count <= 0) return hipSuccess;
+    switch (pat) {
+    case PAT_CYL: launch_sn_pat<PAT_CYL>(d_desc, st, parity, nodes, count, out, s); break;
+    case PAT_ELL: launch_sn_pat<PAT_ELL>(d_desc, st, parity, nodes, count, out, s); break;
+    default: launch_sn_pat<PAT_GEN>(d_desc, st, parity, nodes, count, out, s); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mlbm

@@ -1,0 +1,123 @@
+// Device-side data layout shared by the kernels and the host runtime.
+//
+// HBM layout of one instance:
+//   populations  two buffers (pull: read one, write the other), each
+//                [41][n1][n2][n3] of the storage type, x3 fastest.  Stored
+//                values are offsets from the lattice weights: g = f - w_q
+//                for FP64/FP32, d = f / w_q - 1 for FP16/BF16.
+//   geometry     FP64, structure of arrays [NGEO][n1][n3g] over the cross
+//                section (n3g = 1 when nothing depends on x3, e.g. the
+//                cylinder): Delta^ij = g^ij - delta^ij, Christoffels, unit
+//                force, sqrt(g) and coordinates.  Read through L2.
+//   usnap        FP64 [3][N], lattice velocity at the previous check.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlbm {
+
+enum GeoField {
+    G_D11, G_D12, G_D13, G_D22, G_D23, G_D33,               // Delta^ij (upper)
+    G_1_11, G_1_12, G_1_13, G_1_22, G_1_23, G_1_33,         // Gamma^1_jk (lattice)
+    G_2_11, G_2_12, G_2_13, G_2_22, G_2_23, G_2_33,         // Gamma^2_jk
+    G_3_11, G_3_12, G_3_13, G_3_22, G_3_23, G_3_33,         // Gamma^3_jk
+    G_F1, G_F2, G_F3,                                       // force per unit K (lattice)
+    G_SQRTG,                                                // sqrt(det g) (lattice)
+    G_X1, G_X3,                                             // physical x1, x3 of the node
+    NGEO
+};
+
+// Geometry sparsity the step kernel is compiled for.
+enum Pattern {
+    PAT_CYL = 0,   // diagonal metric, Gamma^1_22 and Gamma^2_12 only (flat, cylinder)
+    PAT_ELL = 1,   // diagonal metric, the six Christoffels of the ellipsoid
+    PAT_GEN = 2,   // full metric and all 18 Christoffels
+};
+
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+
+struct InstDesc {
+    void *f[2];            // population buffers
+    const double *geo;     // [NGEO][n1*n3g]
+    double *usnap;         // [3][N]
+    int n1, n2, n3, walls;
+    int P, N;              // n2*n3, n1*n2*n3
+    int n3g;               // 1 or n3
+    int tpr;               // tiles per x1 row
+    uint64_t n3_magic;     // ceil(2^40 / n3): col / n3 = (col * magic) >> 40
+    double omega;          // 1 / tau
+    double kappa;          // 1 - 1/(2 tau) (improved forcing) or 0 (old)
+    double force;          // covariant body force K
+    double s[3];           // scale factors Dx^i / Dt
+};
+
+// One tile: a run of `block` columns of one x1 row of one instance.
+struct Tile {
+    int inst, x1, chunk, part;   // part: index of its partial sums
+};
+
+struct WindowState {           // per instance, device resident
+    double residual;           // last residual (-1 before two checks)
+    int checks;                // checks done
+    int bad;                   // sticky instability flag
+};
+
+// --- storage codecs ------------------------------------------------------
+
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t h)
+{
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// round to nearest even; NaN stays NaN
+__device__ __forceinline__ uint16_t float_to_bf16_bits(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <int ST> struct Codec;
+
+template <> struct Codec<ST_F64> {
+    using T = double;    // storage
+    using C = double;    // compute
+    __device__ static __forceinline__ C load(const T *p, C) { return *p; }
+    __device__ static __forceinline__ void store(T *p, C g, C) { *p = g; }
+    __device__ static __forceinline__ double to_f64(T v, double) { return v; }
+    __device__ static __forceinline__ T from_f64(double g, double) { return g; }
+};
+
+template <> struct Codec<ST_F32> {
+    using T = float;
+    using C = float;
+    __device__ static __forceinline__ C load(const T *p, C) { return *p; }
+    __device__ static __forceinline__ void store(T *p, C g, C) { *p = g; }
+    __device__ static __forceinline__ double to_f64(T v, double) { return (double)v; }
+    __device__ static __forceinline__ T from_f64(double g, double) { return (float)g; }
+};
+
+template <> struct Codec<ST_F16> {
+    using T = __half;
+    using C = float;
+    __device__ static __forceinline__ C load(const T *p, C w) { return w * __half2float(*p); }
+    __device__ static __forceinline__ void store(T *p, C g, C inv_w) { *p = __float2half_rn(g * inv_w); }
+    __device__ static __forceinline__ double to_f64(T v, double w) { return w * (double)__half2float(v); }
+    __device__ static __forceinline__ T from_f64(double g, double w) { return __float2half_rn((float)(g / w)); }
+};
+
+template <> struct Codec<ST_BF16> {
+    using T = uint16_t;
+    using C = float;
+    __device__ static __forceinline__ C load(const T *p, C w) { return w * bf16_bits_to_float(*p); }
+    __device__ static __forceinline__ void store(T *p, C g, C inv_w) { *p = float_to_bf16_bits(g * inv_w); }
+    __device__ static __forceinline__ double to_f64(T v, double w) { return w * (double)bf16_bits_to_float(v); }
+    __device__ static __forceinline__ T from_f64(double g, double w) { return float_to_bf16_bits((float)(g / w)); }
+};
+
+inline size_t storage_bytes(int st) { return st == ST_F64 ? 8 : st == ST_F32 ? 4 : 2; }
+
+}  // namespace mlbm

@@ -1,0 +1,384 @@
+// Per-node building blocks of the fused step for gfx950:
+//   gather   pull streaming in coordinate space (Eq. (3), left-hand side)
+//            with periodic axes and halfway trajectory bounce-back;
+//   collide  moments, metric Hermite equilibrium through H3 (Eq. (6)),
+//            stress-corrected forcing through H3 and BGK (Eq. (3),
+//            right-hand side), evaluated on (c, -c) pairs.
+//
+// Populations are carried as offsets g_q = f_q - w_q.  Because the weights
+// sum to one and have vanishing odd moments, rho' - 1 = sum g, rho' u = sum c g
+// and sum c c f = sum c c g + cs2 delta, so the offsets lose no information
+// and keep FP32/FP16 rounding small.
+#pragma once
+
+#include <type_traits>
+
+#include "common.hpp"
+#include "lattice.hpp"
+
+namespace mlbm {
+
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// a x + b y + c z for compile-time a, b, c in {-1, 0, 1}; starting from -0.0
+// lets the compiler drop the zero terms exactly.
+template <int A, int B, int Cc, class T>
+__device__ __forceinline__ T sdot(T x, T y, T z)
+{
+    T s = T(-0.0);
+    if constexpr (A == 1) s += x; else if constexpr (A == -1) s -= x;
+    if constexpr (B == 1) s += y; else if constexpr (B == -1) s -= y;
+    if constexpr (Cc == 1) s += z; else if constexpr (Cc == -1) s -= z;
+    return s;
+}
+
+// ------------------------------------------------------------------------
+// Geometry of one cross-section node, with compile-time sparsity
+// ------------------------------------------------------------------------
+
+template <int PAT> struct Mask {
+    // Delta^ij nonzero?
+    static constexpr bool D(int i, int j) { return PAT == PAT_GEN ? true : i == j; }
+    // Gamma^i_jk nonzero (j <= k)?
+    static constexpr bool G(int i, int j, int k)
+    {
+        if (PAT == PAT_GEN) return true;
+        if (PAT == PAT_CYL) return (i == 0 && j == 1 && k == 1) || (i == 1 && j == 0 && k == 1);
+        return (i == 0 && j == 1 && k == 1) || (i == 0 && j == 2 && k == 2) ||
+               (i == 1 && j == 0 && k == 1) || (i == 1 && j == 1 && k == 2) ||
+               (i == 2 && j == 0 && k == 2) || (i == 2 && j == 1 && k == 1);
+    }
+    static constexpr bool F(int i) { return PAT == PAT_GEN ? true : i == 1; }
+};
+
+constexpr int d_field(int i, int j)
+{
+    int a = i < j ? i : j, b = i < j ? j : i;
+    return a == 0 ? (b == 0 ? G_D11 : b == 1 ? G_D12 : G_D13) : a == 1 ? (b == 1 ? G_D22 : G_D23) : G_D33;
+}
+constexpr int g_field(int i, int j, int k)
+{
+    int a = j < k ? j : k, b = j < k ? k : j;
+    int off = a == 0 ? b : a == 1 ? 2 + b : 5;   // (11,12,13,22,23,33) -> 0..5
+    return G_1_11 + 6 * i + off;
+}
+
+template <int PAT, class C>
+struct NodeGeo {
+    C D[3][3];        // Delta^ij (zero entries never read)
+    C Gm[3][3][3];    // Gamma^i_jk (symmetric in jk)
+    C Fe[3];          // external force (lattice units)
+
+    __device__ __forceinline__ void load(const double *__restrict__ geo, int idx, int stride, C force)
+    {
+        static_for<0, 3>([&](auto I) {
+            static_for<0, 3>([&](auto J) {
+                if constexpr (Mask<PAT>::D(I, J)) D[I][J] = (C)geo[d_field(I, J) * stride + idx];
+                static_for<0, 3>([&](auto K) {
+                    if constexpr (Mask<PAT>::G(I, J < K ? J : K, J < K ? K : J))
+                        Gm[I][J][K] = (C)geo[g_field(I, J, K) * stride + idx];
+                });
+            });
+            if constexpr (Mask<PAT>::F(I)) Fe[I] = force * (C)geo[(G_F1 + I) * stride + idx];
+        });
+    }
+};
+
+// ------------------------------------------------------------------------
+// Collision
+// ------------------------------------------------------------------------
+
+// In-place BGK update of one node's offsets g[41] (Sec. II): on return g
+// holds f* - w.  rho_out and u_out receive rho' and the lattice velocity
+// u = sum c f / rho' used by the collision (no half-force shift).
+template <int PAT, class C>
+__device__ __forceinline__ void collide(C (&g)[Q], const NodeGeo<PAT, C> &G, C omega, C kappa,
+                                        C &rho_out, C (&u_out)[3])
+{
+    constexpr C cs2 = (C)CS2;
+    constexpr C ics2 = (C)(1.0 / CS2);
+    constexpr C ics4 = (C)(1.0 / (CS2 * CS2));
+    constexpr C ics6 = (C)(1.0 / (CS2 * CS2 * CS2));
+
+    // --- moments of the offsets
+    C m0 = g[0];
+    C j[3] = {C(-0.0), C(-0.0), C(-0.0)};
+    C p[3][3];
+    static_for<0, 3>([&](auto I) { static_for<0, 3>([&](auto J) { p[I][J] = C(-0.0); }); });
+    static_for<0, NPAIR>([&](auto P) {
+        constexpr int d = PAIR[P][0], k = PAIR[P][1], qp = PAIR[P][2], qm = PAIR[P][3];
+        const C s = g[qp] + g[qm];
+        const C df = g[qp] - g[qm];
+        m0 += s;
+        static_for<0, 3>([&](auto I) {
+            constexpr int ci = DIR[d][I] * k;
+            if constexpr (ci != 0) j[I] += C(ci) * df;
+            static_for<I, 3>([&](auto J) {
+                constexpr int cij = DIR[d][I] * DIR[d][J] * k * k;
+                if constexpr (cij != 0) p[I][J] += C(cij) * s;
+            });
+        });
+    });
+    const C rho = C(1) + m0;
+    const C irho = C(1) / rho;
+    C u[3];
+    static_for<0, 3>([&](auto I) { u[I] = j[I] * irho; });
+    const C uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+
+    // --- per-node quantities
+    C trD = C(-0.0);
+    static_for<0, 3>([&](auto I) { if constexpr (Mask<PAT>::D(I, I)) trD += G.D[I][I]; });
+    // Delta u
+    C Du[3];
+    static_for<0, 3>([&](auto I) {
+        Du[I] = C(-0.0);
+        static_for<0, 3>([&](auto J) { if constexpr (Mask<PAT>::D(I, J)) Du[I] += G.D[I < J ? I : J][I < J ? J : I] * u[J]; });
+    });
+    // a2 = a2_eq + kappa (Pi - Pi_eq), a2_eq = rho (cs2 Delta + u u),
+    // Pi - Pi_eq = sum c c g - cs2 m0 delta - a2_eq
+    C a2[3][3];
+    static_for<0, 3>([&](auto I) {
+        static_for<I, 3>([&](auto J) {
+            C Dij = C(0);
+            if constexpr (Mask<PAT>::D(I, J)) Dij = G.D[I][J];
+            const C A = rho * (cs2 * Dij + u[I] * u[J]);
+            C pn = p[I][J] - A;
+            if constexpr (I == J) pn -= cs2 * m0;
+            a2[I][J] = A + kappa * pn;
+            a2[J][I] = a2[I][J];
+        });
+    });
+    const C tra2 = a2[0][0] + a2[1][1] + a2[2][2];
+    C uFe = C(-0.0);
+    static_for<0, 3>([&](auto I) { if constexpr (Mask<PAT>::F(I)) uFe += u[I] * G.Fe[I]; });
+
+    const C om = omega;
+    const C omw = C(1) - omega;
+    const C wr = omega * rho;
+    // c-independent part of the even coefficient (also the rest population)
+    const C baseE = om * m0 + wr * (C(-0.5) * trD - C(0.5) * ics2 * uu) - rho * ics2 * uFe;
+    const C P0 = wr * (ics2 - C(0.5) * ics4 * uu - C(0.5) * ics2 * trD);
+    const C P1 = wr * (ics6 / C(6));
+    const C P2 = wr * (C(0.5) * ics4);
+    const C Q0 = rho * ics2 - C(0.5) * ics4 * tra2;
+    const C half_ics6 = C(0.5) * ics6;
+    const C rics4 = rho * ics4;
+    const C rics2 = rho * ics2;
+    const C wics2 = wr * ics2;
+
+    g[0] = omw * g[0] + C(W_REST) * baseE;
+
+    // --- 13 unit directions, each used by one or two (k = 1, 3) pairs
+    static_for<0, NDIR>([&](auto Dd) {
+        constexpr int h1 = DIR[Dd][0], h2 = DIR[Dd][1], h3 = DIR[Dd][2];
+        const C cu = sdot<h1, h2, h3>(u[0], u[1], u[2]);
+        const C cDu = sdot<h1, h2, h3>(Du[0], Du[1], Du[2]);
+        // chat Delta chat
+        C cDc = C(-0.0);
+        static_for<0, 3>([&](auto I) {
+            static_for<0, 3>([&](auto J) {
+                constexpr int hh = DIR[Dd][I] * DIR[Dd][J];
+                if constexpr (hh != 0 && Mask<PAT>::D(I, J)) {
+                    if constexpr (hh > 0) cDc += G.D[I < J ? I : J][I < J ? J : I];
+                    else cDc -= G.D[I < J ? I : J][I < J ? J : I];
+                }
+            });
+        });
+        // Gamma(chat, chat)
+        C Gv[3];
+        static_for<0, 3>([&](auto I) {
+            Gv[I] = C(-0.0);
+            static_for<0, 3>([&](auto J) {
+                static_for<0, 3>([&](auto K) {
+                    constexpr int hh = DIR[Dd][J] * DIR[Dd][K];
+                    constexpr int a = J < K ? J : K, b = J < K ? K : J;
+                    if constexpr (hh != 0 && Mask<PAT>::G(I, a, b)) {
+                        if constexpr (hh > 0) Gv[I] += G.Gm[I][J][K];
+                        else Gv[I] -= G.Gm[I][J][K];
+                    }
+                });
+            });
+        });
+        // a2 chat
+        C a2c[3];
+        static_for<0, 3>([&](auto I) { a2c[I] = sdot<h1, h2, h3>(a2[I][0], a2[I][1], a2[I][2]); });
+        const C ca2c = sdot<h1, h2, h3>(a2c[0], a2c[1], a2c[2]);
+        const C Gc = sdot<h1, h2, h3>(Gv[0], Gv[1], Gv[2]);
+        const C uG = u[0] * Gv[0] + u[1] * Gv[1] + u[2] * Gv[2];
+        const C a2cG = a2c[0] * Gv[0] + a2c[1] * Gv[1] + a2c[2] * Gv[2];
+        C Fec = C(-0.0), a2cFe = C(-0.0);
+        static_for<0, 3>([&](auto I) {
+            if constexpr (Mask<PAT>::F(I)) {
+                if constexpr (DIR[Dd][I] == 1) Fec += G.Fe[I];
+                else if constexpr (DIR[Dd][I] == -1) Fec -= G.Fe[I];
+                a2cFe += a2c[I] * G.Fe[I];
+            }
+        });
+
+        static_for<0, NPAIR>([&](auto P) {
+            if constexpr (PAIR[P][0] == Dd) {
+                constexpr int k = PAIR[P][1], qp = PAIR[P][2], qm = PAIR[P][3];
+                constexpr C kk = C(k * k), k3 = C(k * k * k), kf = C(k);
+                const C cuk = kf * cu;
+                const C cuk2 = cuk * cuk;
+                const C Fc = kf * Fec - k3 * Gc;                // F . c
+                const C cDck = kk * cDc;
+                // even part: equilibrium (E - 1) and forcing E_F
+                const C Ev = baseE + wr * (C(0.5) * ics2 * cDck) + P2 * cuk2
+                           + rics4 * cuk * Fc + rics2 * kk * uG;
+                // odd part: equilibrium O and forcing O_F
+                const C Oeq = cuk * (P0 + P1 * cuk2 + P2 * cDck) - wics2 * kf * cDu;
+                const C ca2F = kf * (a2cFe - kk * a2cG);        // c . a2 . F
+                const C OF = Fc * (Q0 + half_ics6 * kk * ca2c) - ics4 * ca2F;
+                const C Od = Oeq + OF;
+                constexpr C w = C(wq(qp));
+                const C te = w * Ev, to = w * Od;
+                g[qp] = omw * g[qp] + (te + to);
+                g[qm] = omw * g[qm] + (te - to);
+            }
+        });
+    });
+    rho_out = rho;
+    u_out[0] = u[0]; u_out[1] = u[1]; u_out[2] = u[2];
+}
+
+// Moments only (for the observables): rho' and u from offsets.
+template <class C>
+__device__ __forceinline__ void moments_only(const C (&g)[Q], C &rho_out, C (&u_out)[3])
+{
+    C m0 = g[0];
+    C j[3] = {C(-0.0), C(-0.0), C(-0.0)};
+    static_for<0, NPAIR>([&](auto P) {
+        constexpr int d = PAIR[P][0], k = PAIR[P][1], qp = PAIR[P][2], qm = PAIR[P][3];
+        m0 += g[qp] + g[qm];
+        const C df = g[qp] - g[qm];
+        static_for<0, 3>([&](auto I) {
+            constexpr int ci = DIR[d][I] * k;
+            if constexpr (ci != 0) j[I] += C(ci) * df;
+        });
+    });
+    rho_out = C(1) + m0;
+    const C ir = C(1) / rho_out;
+    static_for<0, 3>([&](auto I) { u_out[I] = j[I] * ir; });
+}
+
+// ------------------------------------------------------------------------
+// Streaming
+// ------------------------------------------------------------------------
+
+__host__ __device__ __forceinline__ int wrap_axis(int v, int n)
+{
+    while (v < 0) v += n;
+    while (v >= n) v -= n;
+    return v;
+}
+
+constexpr int cslot(int c) { return c == -3 ? 0 : c == -1 ? 1 : c == 0 ? 2 : c == 1 ? 3 : 4; }
+constexpr int CVALS[5] = {-3, -1, 0, 1, 3};
+
+// Per-lane offsets of the pull sources inside an x1 row: o2[s] for the
+// theta shift -CVALS[s] (always periodic, times n3), o3[s] for the x3 shift.
+struct LaneOffsets {
+    int o2[5], o3[5];
+    __device__ __forceinline__ void init(int x2, int x3, int n2, int n3, bool per3)
+    {
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            o2[s] = wrap_axis(x2 - CVALS[s], n2) * n3;
+            o3[s] = per3 ? wrap_axis(x3 - CVALS[s], n3) : x3 - CVALS[s];
+        }
+    }
+};
+
+// Pull from x - c inside the domain (no wall within reach): the row x1 - c1
+// is uniform across the wavefront, only the in-row offset is per lane.
+template <int ST>
+__device__ __forceinline__ void gather_fast(const typename Codec<ST>::T *__restrict__ src,
+                                            const InstDesc &d, int x1, const LaneOffsets &L,
+                                            typename Codec<ST>::C (&g)[Q])
+{
+    using C = typename Codec<ST>::C;
+    const bool per1 = !(d.walls & 1);
+    static_for<0, Q>([&](auto q) {
+        constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
+        int r1 = x1 - c1;
+        if (per1) r1 = wrap_axis(r1, d.n1);
+        const typename Codec<ST>::T *row = src + (size_t)q * d.N + (size_t)r1 * d.P;
+        g[q] = Codec<ST>::load(row + (L.o2[cslot(c2)] + L.o3[cslot(c3)]), (C)wq(q));
+    });
+}
+
+// Source of a pull when a wall may be within reach.  Ticks of 1/(2m) step
+// (m = max |c_a|) put the walls at odd and the nodes at even tick counts.
+// The backward trajectory from x along -c runs inside [-front, back]; it is
+// unfolded to y = front + 2m and folded back into [0, L], L = back + front:
+// crossings n_c = floor(y / L), every crossing reverses the velocity.
+template <int C1, int C2, int C3>
+__host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, int x2, int x3, bool &flip)
+{
+    constexpr int a1 = C1 < 0 ? -C1 : C1, a2 = C2 < 0 ? -C2 : C2, a3 = C3 < 0 ? -C3 : C3;
+    constexpr int m = a1 > a2 ? (a1 > a3 ? a1 : a3) : (a2 > a3 ? a2 : a3);
+    flip = false;
+    if constexpr (m == 0) {
+        return (x1 * d.n2 + x2) * d.n3 + x3;
+    } else {
+        constexpr int h1 = C1 / m, h2 = C2 / m, h3 = C3 / m;
+        int back = 1 << 28, front = 1 << 28;
+        if constexpr (C1 != 0) {
+            if (d.walls & 1) {
+                const int lo = 2 * x1 + 1, hi = 2 * d.n1 - 1 - 2 * x1;
+                back = C1 > 0 ? lo : hi;
+                front = C1 > 0 ? hi : lo;
+            }
+        }
+        if constexpr (C3 != 0) {
+            if (d.walls & 4) {
+                const int lo = 2 * x3 + 1, hi = 2 * d.n3 - 1 - 2 * x3;
+                const int b3 = C3 > 0 ? lo : hi, f3 = C3 > 0 ? hi : lo;
+                back = b3 < back ? b3 : back;
+                front = f3 < front ? f3 : front;
+            }
+        }
+        int sb = m;   // unit steps back along chat
+        if (back < 2 * m) {
+            const int L = back + front;
+            const int y = front + 2 * m;
+            int nc = 0;
+#pragma unroll
+            for (int it = 0; it < 4; ++it) nc += (y > (nc + 1) * L) ? 1 : 0;
+            const int yf = (nc & 1) ? (nc + 1) * L - y : y - nc * L;
+            sb = (yf - front) / 2;
+            flip = nc & 1;
+        }
+        int s1 = x1 - h1 * sb, s2 = x2 - h2 * sb, s3 = x3 - h3 * sb;
+        if (!(d.walls & 1)) s1 = wrap_axis(s1, d.n1);
+        s2 = wrap_axis(s2, d.n2);
+        if (!(d.walls & 4)) s3 = wrap_axis(s3, d.n3);
+        return (s1 * d.n2 + s2) * d.n3 + s3;
+    }
+}
+
+// General pull (any lane position, walls on any axis).
+template <int ST>
+__device__ __forceinline__ void gather_general(const typename Codec<ST>::T *__restrict__ src,
+                                               const InstDesc &d, int x1, int x2, int x3,
+                                               typename Codec<ST>::C (&g)[Q])
+{
+    using C = typename Codec<ST>::C;
+    static_for<0, Q>([&](auto q) {
+        constexpr int qo = opposite(q);
+        bool flip;
+        const int n = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip);
+        const int qs = flip ? qo : (int)q;
+        g[q] = Codec<ST>::load(src + ((size_t)qs * d.N + n), (C)wq(q));
+    });
+}
+
+}  // namespace mlbm

@@ -1,0 +1,135 @@
+// Fused collide-and-stream step for gfx950 (Sec. II, Eq. (3)).
+//
+// One workgroup processes one tile: `blockDim.x` consecutive columns of the
+// (x2, x3) plane of one x1 row of one instance.  Because x1 is uniform per
+// wavefront, the choice between the plain pull and the bounce-back pull,
+// the source row x1 - c1 and the geometry of x3-independent cases are
+// scalar; only the in-row offset of a pull is per lane, so the 41 loads of a
+// node are coalesced runs along x3.  The launch is persistent: workgroups
+// stride over the flat tile queue of all active instances, and the number
+// of queued tiles is read from device memory so that a captured graph stays
+// valid when instances retire.
+//
+// The CHECK variant (every K-th step) also writes the lattice velocity the
+// collision used to the snapshot buffer and reduces, per tile, the squared
+// change against the previous snapshot, the squared velocity and an
+// instability flag (wavefront shuffles, then LDS, fixed order: results are
+// bitwise reproducible).
+#include "core.hpp"
+#include "kernels.hpp"
+
+namespace mlbm {
+
+template <int PAT, int ST, bool CHECK>
+__global__ void __launch_bounds__(512) step_kernel(StepArgs a)
+{
+    using T = typename Codec<ST>::T;
+    using C = typename Codec<ST>::C;
+    __shared__ double red[8][3];
+
+    const int ntiles = *a.ntiles;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const Tile tl = a.tiles[t];
+        const InstDesc &d = a.insts[tl.inst];
+        const int x1 = tl.x1;
+        const int col = tl.chunk * (int)blockDim.x + (int)threadIdx.x;
+        const bool valid = col < d.P;
+        const int colc = valid ? col : 0;
+        const int x2 = (int)(((uint64_t)colc * d.n3_magic) >> 40);
+        const int x3 = colc - x2 * d.n3;
+        const T *__restrict__ src = (const T *)d.f[a.parity];
+        T *__restrict__ dst = (T *)d.f[a.parity ^ 1];
+
+        const bool wall1_row = (d.walls & 1) && (x1 < 3 || x1 > d.n1 - 4);
+        const bool near3 = valid && (d.walls & 4) && (x3 < 3 || x3 > d.n3 - 4);
+        const bool general = wall1_row || (__ballot(near3) != 0);
+
+        double dsq = 0.0, usq = 0.0, badf = 0.0;
+        if (valid) {
+            C g[Q];
+            if (!general) {
+                LaneOffsets L;
+                L.init(x2, x3, d.n2, d.n3, !(d.walls & 4));
+                gather_fast<ST>(src, d, x1, L, g);
+            } else {
+                gather_general<ST>(src, d, x1, x2, x3, g);
+            }
+            const int gidx = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
+            NodeGeo<PAT, C> geo;
+            geo.load(d.geo, gidx, d.n1 * d.n3g, (C)d.force);
+            C rho, u[3];
+            collide<PAT, C>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
+            const size_t n = (size_t)x1 * d.P + col;
+            static_for<0, Q>([&](auto q) {
+                Codec<ST>::store(dst + (size_t)q * d.N + n, g[q], (C)(1.0 / wq(q)));
+            });
+            if constexpr (CHECK) {
+                double *us = d.usnap;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const double v = (double)u[i];
+                    const double dv = v - us[(size_t)i * d.N + n];
+                    dsq += dv * dv;
+                    usq += v * v;
+                    if (!(fabs(v) <= 1.0)) badf = 1.0;
+                    us[(size_t)i * d.N + n] = v;
+                }
+                if (!(rho > C(0))) badf = 1.0;
+            }
+        }
+        if constexpr (CHECK) {
+            for (int off = 32; off > 0; off >>= 1) {
+                dsq += __shfl_xor(dsq, off, 64);
+                usq += __shfl_xor(usq, off, 64);
+                badf += __shfl_xor(badf, off, 64);
+            }
+            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            if (lane == 0) { red[wave][0] = dsq; red[wave][1] = usq; red[wave][2] = badf; }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+                const int nw = (blockDim.x + 63) >> 6;
+                for (int w = 0; w < nw; ++w) { s0 += red[w][0]; s1 += red[w][1]; s2 += red[w][2]; }
+                a.partials[3 * tl.part + 0] = s0;
+                a.partials[3 * tl.part + 1] = s1;
+                a.partials[3 * tl.part + 2] = s2;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+template <int PAT, int ST, bool CHECK>
+static hipError_t launch_one(const StepArgs &a, int grid, int block, hipStream_t s)
+{
+    hipLaunchKernelGGL((step_kernel<PAT, ST, CHECK>), dim3(grid), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int PAT, int ST>
+static hipError_t launch_pst(const StepArgs &a, bool check, int grid, int block, hipStream_t s)
+{
+    return check ? launch_one<PAT, ST, true>(a, grid, block, s) : launch_one<PAT, ST, false>(a, grid, block, s);
+}
+
+template <int PAT>
+static hipError_t launch_pat(const StepArgs &a, int st, bool check, int grid, int block, hipStream_t s)
+{
+    switch (st) {
+    case ST_F64: return launch_pst<PAT, ST_F64>(a, check, grid, block, s);
+    case ST_F32: return launch_pst<PAT, ST_F32>(a, check, grid, block, s);
+    case ST_F16: return launch_pst<PAT, ST_F16>(a, check, grid, block, s);
+    default: return launch_pst<PAT, ST_BF16>(a, check, grid, block, s);
+    }
+}
+
+hipError_t launch_step(const StepArgs &a, int pat, int st, bool check, int grid, int block, hipStream_t s)
+{
+    switch (pat) {
+    case PAT_CYL: return launch_pat<PAT_CYL>(a, st, check, grid, block, s);
+    case PAT_ELL: return launch_pat<PAT_ELL>(a, st, check, grid, block, s);
+    default: return launch_pat<PAT_GEN>(a, st, check, grid, block, s);
+    }
+}
+
+}  // namespace mlbm

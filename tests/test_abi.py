@@ -1,0 +1,89 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, carries the Table I lattice, and its streaming fold (the one the
+kernels run) equals the oracle's pull map.  No kernel is launched."""
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1411_3133_amd import cases as K
+from paper_1411_3133_amd import mlbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(mlbm_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    L = mlbm.load()
+    declared = _declared()
+    assert len(declared) >= 25
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(mlbm.EXPORTS)
+
+
+def test_library_lattice_equals_table1_and_oracle():
+    c, w, cs2 = mlbm.lattice()
+    oc, ow, ocs2, _ = O.lattice()
+    assert np.array_equal(c, oc)
+    assert np.abs(w - ow).max() < 1e-17
+    assert abs(cs2 - ocs2) < 1e-17
+
+
+@pytest.mark.parametrize("n1,n2,n3,walls", [
+    (n1, n2, n3, w) for n1, n2, n3, w in itertools.product([4, 5, 7, 16], [1, 3, 4], [1, 4, 6, 13], [0, 1, 4, 5])
+    if not ((w & 4) and n3 < 4)
+])
+def test_kernel_streaming_fold_equals_oracle_pull_map(n1, n2, n3, walls):
+    case = K.Case(kind="flat", n1=n1, n2=n2, n3=n3, walls=walls, width=1.0)
+    src, sq = mlbm.pull_map(case)
+    assert src.min() >= 0 and src.max() < case.N
+    assert sq.min() >= 0 and sq.max() < 41
+    pm = O.Sim(case).pull_map()
+    assert np.array_equal(src * 41 + sq, pm)
+
+
+def test_kernel_streaming_fold_at_benchmark_sizes():
+    for case in (K.config1(), K.config2_sweep(De_values=[40.0])[0], K.config3_cases()[0]):
+        src, sq = mlbm.pull_map(case)
+        assert src.min() >= 0 and src.max() < case.N
+        flat = src * 41 + sq
+        assert np.array_equal(np.sort(flat.reshape(-1)), np.arange(flat.size))
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n1=0), dict(tau=0.5), dict(tau=0.3), dict(width=0.0), dict(walls=8),
+    dict(n1=3), dict(check_every=3), dict(precision="f64", forcing_mode=2),
+    dict(kind="ellipsoid", b=0.0), dict(kind="ellipsoid", n3=4000, b=1.0),
+])
+def test_invalid_descriptions_are_rejected_before_any_device_work(bad):
+    case = K.config1()
+    for k, v in bad.items():
+        setattr(case, k, v)
+    d, _ = mlbm.make_desc(case) if "forcing_mode" not in bad else mlbm.make_desc(K.config1())
+    if "forcing_mode" in bad:
+        d.forcing_mode = 2
+    import ctypes as C
+    h = C.c_void_p()
+    st = mlbm.load().mlbm_init_geometry(C.byref(d), None, C.byref(h))
+    assert st == mlbm.E_ARG
+    assert mlbm.load().mlbm_last_error()
+
+
+def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(mlbm, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(mlbm, "_lib", None)
+    with pytest.raises(ImportError):
+        mlbm.load()
