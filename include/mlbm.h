@@ -55,7 +55,8 @@ typedef enum {
     MLBM_F64 = 0,         /* populations stored and collided in FP64              */
     MLBM_F32 = 1,         /* stored and collided in FP32                          */
     MLBM_F16 = 2,         /* stored as FP16 offsets f/w - 1, collided in FP32      */
-    MLBM_BF16 = 3         /* stored as BF16 offsets f/w - 1, collided in FP32      */
+    MLBM_BF16 = 3,        /* stored as BF16 offsets f/w - 1, collided in FP32      */
+    MLBM_F32_C64 = 4      /* stored in FP32, collided in FP64                     */
 } mlbm_precision;
 
 enum { MLBM_WALL_AXIS1 = 1, MLBM_WALL_AXIS3 = 4 };

@@ -29,7 +29,7 @@ import numpy as np
 CS2_NOMINAL = 1.0 - math.sqrt(0.4)
 
 KINDS = ("flat", "cylinder", "ellipsoid")
-PRECISIONS = ("f64", "f32", "f16", "bf16")
+PRECISIONS = ("f64", "f32", "f16", "bf16", "f32c64")
 WALL_AXIS1 = 1
 WALL_AXIS3 = 4
 

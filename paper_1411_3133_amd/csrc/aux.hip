@@ -135,6 +135,7 @@ hipError_t launch_init(const InstDesc *d_desc, const InstDesc &h, int st, const 
     case ST_F64: hipLaunchKernelGGL(init_kernel<ST_F64>, grid, block, 0, s, d_desc, init_u, parity); break;
     case ST_F32: hipLaunchKernelGGL(init_kernel<ST_F32>, grid, block, 0, s, d_desc, init_u, parity); break;
     case ST_F16: hipLaunchKernelGGL(init_kernel<ST_F16>, grid, block, 0, s, d_desc, init_u, parity); break;
+    case ST_F32D: hipLaunchKernelGGL(init_kernel<ST_F32D>, grid, block, 0, s, d_desc, init_u, parity); break;
     default: hipLaunchKernelGGL(init_kernel<ST_BF16>, grid, block, 0, s, d_desc, init_u, parity); break;
     }
     return hipGetLastError();
@@ -181,7 +182,7 @@ __device__ __forceinline__ void pull_f64(const InstDesc &d, int parity, int x1, 
         bool flip;
         const int n = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip);
         const int qs = flip ? qo : (int)q;
-        g[q] = Codec<ST>::to_f64(src[(size_t)qs * d.N + n], wq(q));
+        g[q] = Codec<ST>::to_f64(gload<T>(src, sizeof(T) * ((size_t)qs * d.N + n)), wq(q));
     });
 }
 
@@ -211,6 +212,7 @@ hipError_t launch_moments(const InstDesc *d_desc, const InstDesc &h, int st, int
     case ST_F64: hipLaunchKernelGGL(moments_kernel<ST_F64>, grid, block, 0, s, d_desc, parity, rho, u); break;
     case ST_F32: hipLaunchKernelGGL(moments_kernel<ST_F32>, grid, block, 0, s, d_desc, parity, rho, u); break;
     case ST_F16: hipLaunchKernelGGL(moments_kernel<ST_F16>, grid, block, 0, s, d_desc, parity, rho, u); break;
+    case ST_F32D: hipLaunchKernelGGL(moments_kernel<ST_F32D>, grid, block, 0, s, d_desc, parity, rho, u); break;
     default: hipLaunchKernelGGL(moments_kernel<ST_BF16>, grid, block, 0, s, d_desc, parity, rho, u); break;
     }
     return hipGetLastError();
@@ -319,6 +321,7 @@ hipError_t launch_decode(const InstDesc &h, int st, int parity, double *f, hipSt
     case ST_F64: hipLaunchKernelGGL(decode_kernel<ST_F64>, grid, block, 0, s, h, parity, f); break;
     case ST_F32: hipLaunchKernelGGL(decode_kernel<ST_F32>, grid, block, 0, s, h, parity, f); break;
     case ST_F16: hipLaunchKernelGGL(decode_kernel<ST_F16>, grid, block, 0, s, h, parity, f); break;
+    case ST_F32D: hipLaunchKernelGGL(decode_kernel<ST_F32D>, grid, block, 0, s, h, parity, f); break;
     default: hipLaunchKernelGGL(decode_kernel<ST_BF16>, grid, block, 0, s, h, parity, f); break;
     }
     return hipGetLastError();
@@ -332,6 +335,7 @@ hipError_t launch_encode(const InstDesc &h, int st, int parity, const double *f,
     case ST_F64: hipLaunchKernelGGL(encode_kernel<ST_F64>, grid, block, 0, s, h, parity, f); break;
     case ST_F32: hipLaunchKernelGGL(encode_kernel<ST_F32>, grid, block, 0, s, h, parity, f); break;
     case ST_F16: hipLaunchKernelGGL(encode_kernel<ST_F16>, grid, block, 0, s, h, parity, f); break;
+    case ST_F32D: hipLaunchKernelGGL(encode_kernel<ST_F32D>, grid, block, 0, s, h, parity, f); break;
     default: hipLaunchKernelGGL(encode_kernel<ST_BF16>, grid, block, 0, s, h, parity, f); break;
     }
     return hipGetLastError();
@@ -353,16 +357,15 @@ __global__ void step_nodes_kernel(const InstDesc *dd, int parity, const int64_t 
     const int n = (int)nodes[k];
     if (n < 0 || n >= d.N) return;
     const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
-    C g[Q];
-    gather_general<ST>((const T *)d.f[parity], d, x1, x2, x3, g);
+    typename Codec<ST>::G g[Q];
+    gather_general<ST>(d.f[parity], d, x1, x2, x3, g);
     NodeGeo<PAT, C> geo;
     geo.load(d.geo, x1 * d.n3g + (d.n3g > 1 ? x3 : 0), d.n1 * d.n3g, (C)d.force);
     C rho, u[3];
-    collide<PAT, C>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
+    collide<PAT, C, typename Codec<ST>::G>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
     static_for<0, Q>([&](auto q) {
         // round through the storage format, as the step kernel stores it
-        T tmp;
-        Codec<ST>::store(&tmp, g[q], (C)(1.0 / wq(q)));
+        const T tmp = Codec<ST>::encode(g[q], (C)(1.0 / wq(q)));
         out[k * Q + q] = Codec<ST>::to_f64(tmp, wq(q)) + wq(q);
     });
 }
@@ -376,6 +379,7 @@ static void launch_sn_pat(const InstDesc *dd, int st, int parity, const int64_t 
     case ST_F64: hipLaunchKernelGGL((step_nodes_kernel<PAT, ST_F64>), grid, block, 0, s, dd, parity, nodes, count, out); break;
     case ST_F32: hipLaunchKernelGGL((step_nodes_kernel<PAT, ST_F32>), grid, block, 0, s, dd, parity, nodes, count, out); break;
     case ST_F16: hipLaunchKernelGGL((step_nodes_kernel<PAT, ST_F16>), grid, block, 0, s, dd, parity, nodes, count, out); break;
+    case ST_F32D: hipLaunchKernelGGL((step_nodes_kernel<PAT, ST_F32D>), grid, block, 0, s, dd, parity, nodes, count, out); break;
     default: hipLaunchKernelGGL((step_nodes_kernel<PAT, ST_BF16>), grid, block, 0, s, dd, parity, nodes, count, out); break;
     }
 }

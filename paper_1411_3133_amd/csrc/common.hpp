@@ -36,7 +36,7 @@ enum Pattern {
     PAT_GEN = 2,   // full metric and all 18 Christoffels
 };
 
-enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F32D = 4 };
 
 struct InstDesc {
     void *f[2];            // population buffers
@@ -64,6 +64,24 @@ struct WindowState {           // per instance, device resident
     int bad;                   // sticky instability flag
 };
 
+// --- global-memory access ------------------------------------------------
+// Pointers that live inside descriptors are generic to the compiler, which
+// then emits flat loads.  Casting them to the global address space lets it
+// use global loads with a scalar base and a 32-bit per-lane byte offset.
+#define MLBM_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ T gload(const void *base, uint64_t byte_off)
+{
+    return *(const MLBM_GLOBAL T *)((const MLBM_GLOBAL char *)base + byte_off);
+}
+
+template <class T>
+__device__ __forceinline__ void gstore(void *base, uint64_t byte_off, T v)
+{
+    *(MLBM_GLOBAL T *)((MLBM_GLOBAL char *)base + byte_off) = v;
+}
+
 // --- storage codecs ------------------------------------------------------
 
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t h)
@@ -80,13 +98,19 @@ __device__ __forceinline__ uint16_t float_to_bf16_bits(float x)
     return (uint16_t)(u >> 16);
 }
 
+__device__ __forceinline__ float f16_bits_to_float(uint16_t h) { return __half2float(__ushort_as_half(h)); }
+__device__ __forceinline__ uint16_t float_to_f16_bits(float x) { return __half_as_ushort(__float2half_rn(x)); }
+
+// T: stored type; C: compute type.  decode/encode map stored values to and
+// from the offset g = f - w (w = weight of the population).
 template <int ST> struct Codec;
 
 template <> struct Codec<ST_F64> {
-    using T = double;    // storage
-    using C = double;    // compute
-    __device__ static __forceinline__ C load(const T *p, C) { return *p; }
-    __device__ static __forceinline__ void store(T *p, C g, C) { *p = g; }
+    using T = double;
+    using C = double;
+    using G = double;     // register type of the 41 populations
+    __device__ static __forceinline__ C decode(T v, C) { return v; }
+    __device__ static __forceinline__ T encode(C g, C) { return g; }
     __device__ static __forceinline__ double to_f64(T v, double) { return v; }
     __device__ static __forceinline__ T from_f64(double g, double) { return g; }
 };
@@ -94,30 +118,43 @@ template <> struct Codec<ST_F64> {
 template <> struct Codec<ST_F32> {
     using T = float;
     using C = float;
-    __device__ static __forceinline__ C load(const T *p, C) { return *p; }
-    __device__ static __forceinline__ void store(T *p, C g, C) { *p = g; }
+    using G = float;
+    __device__ static __forceinline__ C decode(T v, C) { return v; }
+    __device__ static __forceinline__ T encode(C g, C) { return g; }
+    __device__ static __forceinline__ double to_f64(T v, double) { return (double)v; }
+    __device__ static __forceinline__ T from_f64(double g, double) { return (float)g; }
+};
+
+template <> struct Codec<ST_F32D> {   // FP32 storage, FP64 collision, FP32 registers
+    using T = float;
+    using C = double;
+    using G = float;
+    __device__ static __forceinline__ G decode(T v, C) { return v; }
+    __device__ static __forceinline__ T encode(G g, C) { return g; }
     __device__ static __forceinline__ double to_f64(T v, double) { return (double)v; }
     __device__ static __forceinline__ T from_f64(double g, double) { return (float)g; }
 };
 
 template <> struct Codec<ST_F16> {
-    using T = __half;
+    using T = uint16_t;    // IEEE binary16 bits of d = f / w - 1
     using C = float;
-    __device__ static __forceinline__ C load(const T *p, C w) { return w * __half2float(*p); }
-    __device__ static __forceinline__ void store(T *p, C g, C inv_w) { *p = __float2half_rn(g * inv_w); }
-    __device__ static __forceinline__ double to_f64(T v, double w) { return w * (double)__half2float(v); }
-    __device__ static __forceinline__ T from_f64(double g, double w) { return __float2half_rn((float)(g / w)); }
+    using G = float;
+    __device__ static __forceinline__ C decode(T v, C w) { return w * f16_bits_to_float(v); }
+    __device__ static __forceinline__ T encode(C g, C inv_w) { return float_to_f16_bits(g * inv_w); }
+    __device__ static __forceinline__ double to_f64(T v, double w) { return w * (double)f16_bits_to_float(v); }
+    __device__ static __forceinline__ T from_f64(double g, double w) { return float_to_f16_bits((float)(g / w)); }
 };
 
 template <> struct Codec<ST_BF16> {
-    using T = uint16_t;
+    using T = uint16_t;    // bfloat16 bits of d = f / w - 1
     using C = float;
-    __device__ static __forceinline__ C load(const T *p, C w) { return w * bf16_bits_to_float(*p); }
-    __device__ static __forceinline__ void store(T *p, C g, C inv_w) { *p = float_to_bf16_bits(g * inv_w); }
+    using G = float;
+    __device__ static __forceinline__ C decode(T v, C w) { return w * bf16_bits_to_float(v); }
+    __device__ static __forceinline__ T encode(C g, C inv_w) { return float_to_bf16_bits(g * inv_w); }
     __device__ static __forceinline__ double to_f64(T v, double w) { return w * (double)bf16_bits_to_float(v); }
     __device__ static __forceinline__ T from_f64(double g, double w) { return float_to_bf16_bits((float)(g / w)); }
 };
 
-inline size_t storage_bytes(int st) { return st == ST_F64 ? 8 : st == ST_F32 ? 4 : 2; }
+inline size_t storage_bytes(int st) { return st == ST_F64 ? 8 : (st == ST_F32 || st == ST_F32D) ? 4 : 2; }
 
 }  // namespace mlbm

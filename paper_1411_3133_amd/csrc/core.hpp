@@ -19,7 +19,7 @@
 namespace mlbm {
 
 template <int I, int N, class F>
-__device__ __forceinline__ void static_for(F &&f)
+__host__ __device__ __forceinline__ void static_for(F &&f)
 {
     if constexpr (I < N) {
         f(std::integral_constant<int, I>{});
@@ -30,7 +30,7 @@ __device__ __forceinline__ void static_for(F &&f)
 // a x + b y + c z for compile-time a, b, c in {-1, 0, 1}; starting from -0.0
 // lets the compiler drop the zero terms exactly.
 template <int A, int B, int Cc, class T>
-__device__ __forceinline__ T sdot(T x, T y, T z)
+__host__ __device__ __forceinline__ T sdot(T x, T y, T z)
 {
     T s = T(-0.0);
     if constexpr (A == 1) s += x; else if constexpr (A == -1) s -= x;
@@ -80,13 +80,15 @@ struct NodeGeo {
     {
         static_for<0, 3>([&](auto I) {
             static_for<0, 3>([&](auto J) {
-                if constexpr (Mask<PAT>::D(I, J)) D[I][J] = (C)geo[d_field(I, J) * stride + idx];
+                if constexpr (Mask<PAT>::D(I, J))
+                    D[I][J] = (C)gload<double>(geo, 8ull * ((uint32_t)(d_field(I, J) * stride) + (uint32_t)idx));
                 static_for<0, 3>([&](auto K) {
                     if constexpr (Mask<PAT>::G(I, J < K ? J : K, J < K ? K : J))
-                        Gm[I][J][K] = (C)geo[g_field(I, J, K) * stride + idx];
+                        Gm[I][J][K] = (C)gload<double>(geo, 8ull * ((uint32_t)(g_field(I, J, K) * stride) + (uint32_t)idx));
                 });
             });
-            if constexpr (Mask<PAT>::F(I)) Fe[I] = force * (C)geo[(G_F1 + I) * stride + idx];
+            if constexpr (Mask<PAT>::F(I))
+                Fe[I] = force * (C)gload<double>(geo, 8ull * ((uint32_t)((G_F1 + I) * stride) + (uint32_t)idx));
         });
     }
 };
@@ -97,10 +99,12 @@ struct NodeGeo {
 
 // In-place BGK update of one node's offsets g[41] (Sec. II): on return g
 // holds f* - w.  rho_out and u_out receive rho' and the lattice velocity
-// u = sum c f / rho' used by the collision (no half-force shift).
-template <int PAT, class C>
-__device__ __forceinline__ void collide(C (&g)[Q], const NodeGeo<PAT, C> &G, C omega, C kappa,
-                                        C &rho_out, C (&u_out)[3])
+// u = sum c f / rho' used by the collision (no half-force shift).  R is the
+// register type of the populations, C the arithmetic type (R may be
+// narrower: every value is widened to C before it is used).
+template <int PAT, class C, class R>
+__host__ __device__ __forceinline__ void collide(R (&g)[Q], const NodeGeo<PAT, C> &G, C omega, C kappa,
+                                                 C &rho_out, C (&u_out)[3])
 {
     constexpr C cs2 = (C)CS2;
     constexpr C ics2 = (C)(1.0 / CS2);
@@ -108,14 +112,15 @@ __device__ __forceinline__ void collide(C (&g)[Q], const NodeGeo<PAT, C> &G, C o
     constexpr C ics6 = (C)(1.0 / (CS2 * CS2 * CS2));
 
     // --- moments of the offsets
-    C m0 = g[0];
+    C m0 = (C)g[0];
     C j[3] = {C(-0.0), C(-0.0), C(-0.0)};
     C p[3][3];
     static_for<0, 3>([&](auto I) { static_for<0, 3>([&](auto J) { p[I][J] = C(-0.0); }); });
     static_for<0, NPAIR>([&](auto P) {
         constexpr int d = PAIR[P][0], k = PAIR[P][1], qp = PAIR[P][2], qm = PAIR[P][3];
-        const C s = g[qp] + g[qm];
-        const C df = g[qp] - g[qm];
+        const C gp = (C)g[qp], gm = (C)g[qm];
+        const C s = gp + gm;
+        const C df = gp - gm;
         m0 += s;
         static_for<0, 3>([&](auto I) {
             constexpr int ci = DIR[d][I] * k;
@@ -173,7 +178,16 @@ __device__ __forceinline__ void collide(C (&g)[Q], const NodeGeo<PAT, C> &G, C o
     const C rics2 = rho * ics2;
     const C wics2 = wr * ics2;
 
-    g[0] = omw * g[0] + C(W_REST) * baseE;
+    // FP32 arithmetic tracks the mass and momentum the rounded update actually
+    // moves (sums of the small per-population changes, exact differences of
+    // nearby floats) so that they can be set to their exact values below.
+    constexpr bool CONSERVE = sizeof(C) == 4;
+    C dm = C(-0.0), dj[3] = {C(-0.0), C(-0.0), C(-0.0)};
+    {
+        const R n0 = (R)(omw * (C)g[0] + C(W_REST) * baseE);
+        if constexpr (CONSERVE) dm += (C)n0 - (C)g[0];
+        g[0] = n0;
+    }
 
     // --- 13 unit directions, each used by one or two (k = 1, 3) pairs
     static_for<0, NDIR>([&](auto Dd) {
@@ -240,11 +254,59 @@ __device__ __forceinline__ void collide(C (&g)[Q], const NodeGeo<PAT, C> &G, C o
                 const C Od = Oeq + OF;
                 constexpr C w = C(wq(qp));
                 const C te = w * Ev, to = w * Od;
-                g[qp] = omw * g[qp] + (te + to);
-                g[qm] = omw * g[qm] + (te - to);
+                const R np = (R)(omw * (C)g[qp] + (te + to));
+                const R nm = (R)(omw * (C)g[qm] + (te - to));
+                if constexpr (CONSERVE) {
+                    const C dp = (C)np - (C)g[qp], dq = (C)nm - (C)g[qm];
+                    dm += dp + dq;
+                    const C dd = dp - dq;
+                    static_for<0, 3>([&](auto I) {
+                        constexpr int ci = DIR[Dd][I] * k;
+                        if constexpr (ci != 0) dj[I] += C(ci) * dd;
+                    });
+                }
+                g[qp] = np;
+                g[qm] = nm;
             }
         });
     });
+    // In exact arithmetic the update changes the mass by sum F = -2 rho' u^i
+    // Gamma^k_ki and the momentum by S^m = rho' F_ext^m - Gamma^m_jk M^jk -
+    // 2 Gamma^k_kj M^mj, M = rho' cs2 delta + a2 (moments of the forcing
+    // term).  Float weights and constants miss these by a relative ~1e-7 with
+    // the same sign at every node, which acts as a spurious body force in
+    // slowly damped flows; the defect goes into the rest population (mass)
+    // and the +-e_i pairs (momentum).
+    if constexpr (CONSERVE) {
+        C tr[3];   // Gamma^k_ki
+        static_for<0, 3>([&](auto I) {
+            tr[I] = C(-0.0);
+            static_for<0, 3>([&](auto K) {
+                constexpr int a = K < I ? K : I, b = K < I ? I : K;
+                if constexpr (Mask<PAT>::G(K, a, b)) tr[I] += G.Gm[K][K][I];
+            });
+        });
+        const C dm_exp = C(-2) * rho * (u[0] * tr[0] + u[1] * tr[1] + u[2] * tr[2]);
+        g[0] = (R)((C)g[0] + (dm_exp - dm));
+        static_for<0, 3>([&](auto I) {
+            C s = C(-0.0);
+            if constexpr (Mask<PAT>::F(I)) s += rho * G.Fe[I];
+            static_for<0, 3>([&](auto J) {
+                const C MIJ = (I == J) ? a2[I][J] + rho * cs2 : a2[I][J];
+                static_for<0, 3>([&](auto K) {
+                    constexpr int a = J < K ? J : K, b = J < K ? K : J;
+                    if constexpr (Mask<PAT>::G(I, a, b)) {
+                        const C MJK = (J == K) ? a2[J][K] + rho * cs2 : a2[J][K];
+                        s -= G.Gm[I][J][K] * MJK;
+                    }
+                });
+                s -= C(2) * tr[J] * MIJ;
+            });
+            const C h = C(0.5) * (s - dj[I]);
+            g[1 + 2 * I] = (R)((C)g[1 + 2 * I] + h);
+            g[2 + 2 * I] = (R)((C)g[2 + 2 * I] - h);
+        });
+    }
     rho_out = rho;
     u_out[0] = u[0]; u_out[1] = u[1]; u_out[2] = u[2];
 }
@@ -283,35 +345,37 @@ __host__ __device__ __forceinline__ int wrap_axis(int v, int n)
 constexpr int cslot(int c) { return c == -3 ? 0 : c == -1 ? 1 : c == 0 ? 2 : c == 1 ? 3 : 4; }
 constexpr int CVALS[5] = {-3, -1, 0, 1, 3};
 
-// Per-lane offsets of the pull sources inside an x1 row: o2[s] for the
-// theta shift -CVALS[s] (always periodic, times n3), o3[s] for the x3 shift.
+// Per-lane byte offsets of the pull sources inside an x1 row: o2[s] for the
+// theta shift -CVALS[s] (always periodic), o3[s] for the x3 shift.
 struct LaneOffsets {
-    int o2[5], o3[5];
-    __device__ __forceinline__ void init(int x2, int x3, int n2, int n3, bool per3)
+    uint32_t o2[5], o3[5];
+    __device__ __forceinline__ void init(int x2, int x3, int n2, int n3, bool per3, uint32_t S)
     {
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
-            o2[s] = wrap_axis(x2 - CVALS[s], n2) * n3;
-            o3[s] = per3 ? wrap_axis(x3 - CVALS[s], n3) : x3 - CVALS[s];
+            o2[s] = (uint32_t)(wrap_axis(x2 - CVALS[s], n2) * n3) * S;
+            o3[s] = (uint32_t)(per3 ? wrap_axis(x3 - CVALS[s], n3) : x3 - CVALS[s]) * S;
         }
     }
 };
 
 // Pull from x - c inside the domain (no wall within reach): the row x1 - c1
-// is uniform across the wavefront, only the in-row offset is per lane.
+// is uniform across the wavefront, only the in-row byte offset is per lane.
 template <int ST>
-__device__ __forceinline__ void gather_fast(const typename Codec<ST>::T *__restrict__ src,
-                                            const InstDesc &d, int x1, const LaneOffsets &L,
-                                            typename Codec<ST>::C (&g)[Q])
+__device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, int x1, const LaneOffsets &L,
+                                            typename Codec<ST>::G (&g)[Q])
 {
+    using T = typename Codec<ST>::T;
     using C = typename Codec<ST>::C;
+    constexpr uint64_t S = sizeof(T);
     const bool per1 = !(d.walls & 1);
     static_for<0, Q>([&](auto q) {
         constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
         int r1 = x1 - c1;
         if (per1) r1 = wrap_axis(r1, d.n1);
-        const typename Codec<ST>::T *row = src + (size_t)q * d.N + (size_t)r1 * d.P;
-        g[q] = Codec<ST>::load(row + (L.o2[cslot(c2)] + L.o3[cslot(c3)]), (C)wq(q));
+        const uint64_t row = ((uint64_t)q * (uint64_t)d.N + (uint64_t)r1 * (uint64_t)d.P) * S;
+        const void *rowp = (const char *)src + row;
+        g[q] = Codec<ST>::decode(gload<T>(rowp, L.o2[cslot(c2)] + L.o3[cslot(c3)]), (C)wq(q));
     });
 }
 
@@ -367,17 +431,18 @@ __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, i
 
 // General pull (any lane position, walls on any axis).
 template <int ST>
-__device__ __forceinline__ void gather_general(const typename Codec<ST>::T *__restrict__ src,
-                                               const InstDesc &d, int x1, int x2, int x3,
-                                               typename Codec<ST>::C (&g)[Q])
+__device__ __forceinline__ void gather_general(const void *src, const InstDesc &d, int x1, int x2, int x3,
+                                               typename Codec<ST>::G (&g)[Q])
 {
+    using T = typename Codec<ST>::T;
     using C = typename Codec<ST>::C;
+    constexpr uint32_t S = sizeof(T);
     static_for<0, Q>([&](auto q) {
         constexpr int qo = opposite(q);
         bool flip;
         const int n = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip);
-        const int qs = flip ? qo : (int)q;
-        g[q] = Codec<ST>::load(src + ((size_t)qs * d.N + n), (C)wq(q));
+        const uint32_t qs = flip ? (uint32_t)qo : (uint32_t)q;
+        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)((qs * (uint32_t)d.N + (uint32_t)n) * S)), (C)wq(q));
     });
 }
 

@@ -37,8 +37,9 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
         const int colc = valid ? col : 0;
         const int x2 = (int)(((uint64_t)colc * d.n3_magic) >> 40);
         const int x3 = colc - x2 * d.n3;
-        const T *__restrict__ src = (const T *)d.f[a.parity];
-        T *__restrict__ dst = (T *)d.f[a.parity ^ 1];
+        const void *src = d.f[a.parity];
+        void *dst = d.f[a.parity ^ 1];
+        constexpr uint32_t S = sizeof(T);
 
         const bool wall1_row = (d.walls & 1) && (x1 < 3 || x1 > d.n1 - 4);
         const bool near3 = valid && (d.walls & 4) && (x3 < 3 || x3 > d.n3 - 4);
@@ -46,10 +47,10 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
 
         double dsq = 0.0, usq = 0.0, badf = 0.0;
         if (valid) {
-            C g[Q];
+            typename Codec<ST>::G g[Q];
             if (!general) {
                 LaneOffsets L;
-                L.init(x2, x3, d.n2, d.n3, !(d.walls & 4));
+                L.init(x2, x3, d.n2, d.n3, !(d.walls & 4), S);
                 gather_fast<ST>(src, d, x1, L, g);
             } else {
                 gather_general<ST>(src, d, x1, x2, x3, g);
@@ -58,21 +59,25 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
             NodeGeo<PAT, C> geo;
             geo.load(d.geo, gidx, d.n1 * d.n3g, (C)d.force);
             C rho, u[3];
-            collide<PAT, C>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
+            collide<PAT, C, typename Codec<ST>::G>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
             const size_t n = (size_t)x1 * d.P + col;
+            void *drow = (char *)dst + (uint64_t)x1 * (uint64_t)d.P * S;
+            const uint32_t loff = (uint32_t)col * S;
             static_for<0, Q>([&](auto q) {
-                Codec<ST>::store(dst + (size_t)q * d.N + n, g[q], (C)(1.0 / wq(q)));
+                void *plane = (char *)drow + (uint64_t)q * (uint64_t)d.N * S;
+                gstore<T>(plane, loff, Codec<ST>::encode(g[q], (C)(1.0 / wq(q))));
             });
             if constexpr (CHECK) {
                 double *us = d.usnap;
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
                     const double v = (double)u[i];
-                    const double dv = v - us[(size_t)i * d.N + n];
+                    const uint64_t off = 8ull * ((uint64_t)i * d.N + n);
+                    const double dv = v - gload<double>(us, off);
                     dsq += dv * dv;
                     usq += v * v;
                     if (!(fabs(v) <= 1.0)) badf = 1.0;
-                    us[(size_t)i * d.N + n] = v;
+                    gstore<double>(us, off, v);
                 }
                 if (!(rho > C(0))) badf = 1.0;
             }
@@ -119,6 +124,7 @@ static hipError_t launch_pat(const StepArgs &a, int st, bool check, int grid, in
     case ST_F64: return launch_pst<PAT, ST_F64>(a, check, grid, block, s);
     case ST_F32: return launch_pst<PAT, ST_F32>(a, check, grid, block, s);
     case ST_F16: return launch_pst<PAT, ST_F16>(a, check, grid, block, s);
+    case ST_F32D: return launch_pst<PAT, ST_F32D>(a, check, grid, block, s);
     default: return launch_pst<PAT, ST_BF16>(a, check, grid, block, s);
     }
 }

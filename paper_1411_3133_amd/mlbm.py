@@ -20,7 +20,7 @@ Q = 41
 
 OK, E_ARG, E_HIP, E_OOM, E_UNSTABLE, E_STATE, E_IO = range(7)
 KIND = {"flat": 0, "cylinder": 1, "ellipsoid": 2}
-PRECISION = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+PRECISION = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32c64": 4}
 
 
 class MlbmError(RuntimeError):
