@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--precision", default="f32", choices=list(BYTES))
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--block", type=int, default=0, help="force the workgroup size (skips the autotuner)")
+    ap.add_argument("--grid", type=int, default=0, help="persistent grid with --block (0: one workgroup per tile)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
@@ -106,7 +108,10 @@ def main():
     batch = mlbm.Batch(cases, inits, stream=stream)
     nodes = sum(c.N for c in cases)
     block, grid = (256, 0)
-    if not args.no_autotune:
+    if args.block:
+        block, grid = args.block, args.grid
+        batch.set_launch(block, grid)
+    elif not args.no_autotune:
         block, grid = batch.autotune(steps=20)
     batch.step(args.warmup)
     torch.cuda.synchronize()
