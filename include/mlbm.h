@@ -207,6 +207,59 @@ double mlbm_batch_last_step_ms(mlbm_batch b);
 int mlbm_batch_size(mlbm_batch b);
 void mlbm_batch_destroy(mlbm_batch b);
 
+/* ---------------- learned warm start ------------------------------------ */
+
+/* A fully connected network 5 -> H -> ... -> H -> 3 (`depth` hidden layers,
+ * SiLU, linear output, FP32) that maps (De, R1/d, R2/d, r, arc position) of a
+ * cross-section node to its steady physical velocity over the nominal mean
+ * speed; its prediction initialises a run instead of the laminar profile.
+ * Parameters: per layer W [n_out][n_in] row-major, then b [n_out]. */
+typedef struct mlbm_net_s *mlbm_net;
+
+/* Number of parameters, or -1 if the shape is not supported (H in {32, 64},
+ * 1 <= depth <= 6, parameters within 64 KiB). */
+int64_t mlbm_net_num_params(int hidden, int depth);
+
+/* Create a network from caller-owned initial parameters (host, copied). */
+mlbm_status mlbm_net_create(int hidden, int depth, const double *init_params, void *hip_stream, mlbm_net *out);
+void mlbm_net_destroy(mlbm_net n);
+const char *mlbm_net_last_error(void);
+
+/* Copy the parameters out (get = 1) or in (get = 0), host array. */
+mlbm_status mlbm_net_params(mlbm_net n, double *params, int get);
+
+/* Forward pass of n samples: x [n][5] -> y [n][3], host arrays. */
+mlbm_status mlbm_net_forward(mlbm_net net, const float *x, int64_t n, float *y);
+
+/* Mean squared error 1/(3n) sum (y - t)^2 of n samples (host arrays) and its
+ * gradient with respect to the parameters (host, may be NULL); the gradient
+ * stays on the device for mlbm_net_adam_step. */
+mlbm_status mlbm_net_gradient(mlbm_net net, const float *x, const float *t, int64_t n, double *loss, double *grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the last gradient. */
+mlbm_status mlbm_net_adam_step(mlbm_net net, double lr);
+
+/* Append the cross-section nodes (theta slab 0) of a case to the device
+ * training set: inputs from the description and (De, R1/d, R2/d), targets
+ * from its velocity field u [3][N] (physical contravariant, e.g. from
+ * mlbm_moments; host or device per on_device) over U_nom. */
+mlbm_status mlbm_net_dataset_add(mlbm_net net, const mlbm_desc *d, double De, double R1_d, double R2_d,
+                                 double U_nom, const double *u, int on_device);
+mlbm_status mlbm_net_dataset_clear(mlbm_net net);
+int64_t mlbm_net_dataset_size(mlbm_net net);
+
+/* `steps` Adam steps on minibatches of `batch` samples drawn from the training
+ * set by a counter-based hash of `seed`; *last_loss: loss of the last batch. */
+mlbm_status mlbm_net_train(mlbm_net net, int64_t steps, int64_t batch, double lr, uint64_t seed, double *last_loss);
+
+/* Loss over the whole training set. */
+mlbm_status mlbm_net_dataset_loss(mlbm_net net, double *loss);
+
+/* Predicted velocity field of a case, physical contravariant [3][N] (every
+ * theta slab), ready to pass as mlbm_desc.init_u; host or device buffer. */
+mlbm_status mlbm_warmstart_predict(mlbm_net net, const mlbm_desc *d, double De, double R1_d, double R2_d,
+                                   double U_nom, double *u_out, int on_device);
+
 #ifdef __cplusplus
 }
 #endif

@@ -223,3 +223,47 @@ class Sim:
 
 def threads():
     return lib().orc_threads()
+
+
+# --------------------------------------------------------------------------
+# warm-start network (mlp_oracle.c)
+# --------------------------------------------------------------------------
+
+def _mlp_lib():
+    L = lib()
+    if not getattr(L, "_mlp_ready", False):
+        L.mlp_num_params.argtypes = [C.c_int, C.c_int]
+        L.mlp_num_params.restype = C.c_long
+        L.mlp_forward.argtypes = [_dp, C.c_int, C.c_int, _dp, C.c_long, _dp]
+        L.mlp_gradient.argtypes = [_dp, C.c_int, C.c_int, _dp, _dp, C.c_long, _dp]
+        L.mlp_gradient.restype = C.c_double
+        L.mlp_adam.argtypes = [_dp, _dp, _dp, _dp, C.c_long, C.c_double, C.c_double, C.c_double,
+                               C.c_double, C.c_long]
+        L._mlp_ready = True
+    return L
+
+
+def mlp_num_params(H, depth):
+    return _mlp_lib().mlp_num_params(H, depth)
+
+
+def mlp_forward(p, H, depth, x):
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.zeros((len(x), 3))
+    _mlp_lib().mlp_forward(np.ascontiguousarray(p, np.float64), H, depth, x.reshape(-1), len(x), y.reshape(-1))
+    return y
+
+
+def mlp_gradient(p, H, depth, x, t):
+    x = np.ascontiguousarray(x, np.float64)
+    t = np.ascontiguousarray(t, np.float64)
+    g = np.zeros(len(p))
+    loss = _mlp_lib().mlp_gradient(np.ascontiguousarray(p, np.float64), H, depth, x.reshape(-1),
+                                   t.reshape(-1), len(x), g)
+    return loss, g
+
+
+def mlp_adam(p, g, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    p = np.array(p, np.float64); m = np.array(m, np.float64); v = np.array(v, np.float64)
+    _mlp_lib().mlp_adam(p, np.ascontiguousarray(g, np.float64), m, v, len(p), lr, b1, b2, eps, t)
+    return p, m, v

@@ -305,3 +305,24 @@ def config4_batch(seed: int = 3133, n_pairs: int = 8, per_pair: int = 8,
             cases.append(ellipsoid_case(R1, R2, n1, 4, n3, tau, De=De, precision=precision,
                                         label=f"C4-p{p}-k{k}"))
     return cases
+
+
+# --------------------------------------------------------------------------
+# Warm-start network: seeded initial parameters
+# --------------------------------------------------------------------------
+
+def net_shape(hidden: int, depth: int):
+    """[(n_in, n_out)] per layer of the 5 -> hidden^depth -> 3 network."""
+    sizes = [5] + [hidden] * depth + [3]
+    return list(zip(sizes[:-1], sizes[1:]))
+
+
+def net_init_params(hidden: int, depth: int, seed: int = 2024) -> np.ndarray:
+    """Glorot-uniform weights, zero biases, in the library's parameter order
+    (per layer W [n_out][n_in] row-major, then b [n_out])."""
+    out = []
+    for l, (ni, no) in enumerate(net_shape(hidden, depth)):
+        a = math.sqrt(6.0 / (ni + no))
+        out.append(a * uniform_pm1(seed, ni * no, stream=100 + l))
+        out.append(np.zeros(no))
+    return np.concatenate(out)

@@ -47,6 +47,10 @@ EXPORTS = [
     "mlbm_batch_create", "mlbm_batch_step", "mlbm_batch_run_until", "mlbm_batch_get",
     "mlbm_batch_set_launch", "mlbm_batch_autotune", "mlbm_batch_use_graph",
     "mlbm_batch_last_step_ms", "mlbm_batch_size", "mlbm_batch_destroy",
+    "mlbm_net_num_params", "mlbm_net_create", "mlbm_net_destroy", "mlbm_net_last_error",
+    "mlbm_net_params", "mlbm_net_forward", "mlbm_net_gradient", "mlbm_net_adam_step",
+    "mlbm_net_dataset_add", "mlbm_net_dataset_clear", "mlbm_net_dataset_size", "mlbm_net_train",
+    "mlbm_net_dataset_loss", "mlbm_warmstart_predict",
 ]
 
 _lib = None
@@ -92,6 +96,25 @@ def load():
     L.mlbm_batch_size.argtypes = [vp]
     L.mlbm_batch_destroy.argtypes = [vp]
     L.mlbm_batch_destroy.restype = None
+    L.mlbm_net_num_params.argtypes = [C.c_int, C.c_int]
+    L.mlbm_net_num_params.restype = i64
+    L.mlbm_net_create.argtypes = [C.c_int, C.c_int, vp, vp, C.POINTER(vp)]
+    L.mlbm_net_destroy.argtypes = [vp]
+    L.mlbm_net_destroy.restype = None
+    L.mlbm_net_last_error.restype = C.c_char_p
+    L.mlbm_net_params.argtypes = [vp, vp, C.c_int]
+    L.mlbm_net_forward.argtypes = [vp, vp, i64, vp]
+    L.mlbm_net_gradient.argtypes = [vp, vp, vp, i64, dp, vp]
+    L.mlbm_net_adam_step.argtypes = [vp, C.c_double]
+    L.mlbm_net_dataset_add.argtypes = [vp, C.POINTER(Desc), C.c_double, C.c_double, C.c_double, C.c_double,
+                                       vp, C.c_int]
+    L.mlbm_net_dataset_clear.argtypes = [vp]
+    L.mlbm_net_dataset_size.argtypes = [vp]
+    L.mlbm_net_dataset_size.restype = i64
+    L.mlbm_net_train.argtypes = [vp, i64, i64, C.c_double, C.c_uint64, dp]
+    L.mlbm_net_dataset_loss.argtypes = [vp, dp]
+    L.mlbm_warmstart_predict.argtypes = [vp, C.POINTER(Desc), C.c_double, C.c_double, C.c_double, C.c_double,
+                                         vp, C.c_int]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -302,3 +325,95 @@ class Batch:
 
     def use_graph(self, on: bool):
         _check(load().mlbm_batch_use_graph(self._h, 1 if on else 0))
+
+
+def _net_check(status):
+    if status != OK:
+        raise MlbmError(status, load().mlbm_net_last_error().decode(errors="replace"))
+
+
+class Net:
+    """The warm-start network (kernels in csrc/mlp.hip)."""
+
+    def __init__(self, hidden: int, depth: int, params, stream=None):
+        L = load()
+        self.hidden, self.depth = hidden, depth
+        self.np = int(L.mlbm_net_num_params(hidden, depth))
+        if self.np < 0:
+            raise ValueError("unsupported network shape")
+        p = np.ascontiguousarray(params, np.float64)
+        if p.size != self.np:
+            raise ValueError(f"expected {self.np} parameters")
+        h = C.c_void_p()
+        _net_check(L.mlbm_net_create(hidden, depth, p.ctypes.data_as(C.c_void_p), _stream_arg(stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().mlbm_net_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def params(self):
+        p = np.zeros(self.np)
+        _net_check(load().mlbm_net_params(self._h, p.ctypes.data_as(C.c_void_p), 1))
+        return p
+
+    @params.setter
+    def params(self, value):
+        p = np.ascontiguousarray(value, np.float64)
+        _net_check(load().mlbm_net_params(self._h, p.ctypes.data_as(C.c_void_p), 0))
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.zeros((len(x), 3), np.float32)
+        _net_check(load().mlbm_net_forward(self._h, x.ctypes.data_as(C.c_void_p), len(x), y.ctypes.data_as(C.c_void_p)))
+        return y
+
+    def gradient(self, x, t):
+        x = np.ascontiguousarray(x, np.float32)
+        t = np.ascontiguousarray(t, np.float32)
+        g = np.zeros(self.np)
+        loss = C.c_double()
+        _net_check(load().mlbm_net_gradient(self._h, x.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p),
+                                            len(x), C.byref(loss), g.ctypes.data_as(C.c_void_p)))
+        return loss.value, g
+
+    def adam_step(self, lr):
+        _net_check(load().mlbm_net_adam_step(self._h, float(lr)))
+
+    def dataset_add(self, case: Case, u, De, R1_d, R2_d, U_nom):
+        d, _ = make_desc(case)
+        u = np.ascontiguousarray(u, np.float64).reshape(-1)
+        _net_check(load().mlbm_net_dataset_add(self._h, C.byref(d), float(De), float(R1_d), float(R2_d),
+                                               float(U_nom), u.ctypes.data_as(C.c_void_p), 0))
+
+    def dataset_clear(self):
+        _net_check(load().mlbm_net_dataset_clear(self._h))
+
+    @property
+    def dataset_size(self):
+        return int(load().mlbm_net_dataset_size(self._h))
+
+    def train(self, steps, batch=4096, lr=1e-3, seed=1):
+        loss = C.c_double()
+        _net_check(load().mlbm_net_train(self._h, int(steps), int(batch), float(lr), int(seed), C.byref(loss)))
+        return loss.value
+
+    def dataset_loss(self):
+        loss = C.c_double()
+        _net_check(load().mlbm_net_dataset_loss(self._h, C.byref(loss)))
+        return loss.value
+
+    def predict(self, case: Case, De, R1_d, R2_d, U_nom):
+        d, _ = make_desc(case)
+        u = np.zeros(3 * case.N)
+        _net_check(load().mlbm_warmstart_predict(self._h, C.byref(d), float(De), float(R1_d), float(R2_d),
+                                                 float(U_nom), u.ctypes.data_as(C.c_void_p), 0))
+        return u.reshape(3, case.n1, case.n2, case.n3)
