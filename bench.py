@@ -68,6 +68,67 @@ def cpu_baseline(case, init, budget_s=12.0):
                       f"{steps} steps, {dt:.1f} s, FP64"}
 
 
+def time_to_steady(n_train, n_test, tol=1e-6, cap=150000):
+    """Time to residual <= tol on unseen small double-curved channels, three
+    ways on the same GPU: (i) plain laminar start, one instance at a time;
+    (ii) plain start, all cases in one batch; (iii) batch started from the
+    network's prediction. The network is trained on the GPU on steady fields
+    that the batched solver produces for other cases; producing them and
+    training are reported separately, inference is included in (iii)."""
+    import numpy as np
+    from paper_1411_3133_amd import cases as K
+    from paper_1411_3133_amd import mlbm
+    from paper_1411_3133_amd import warmstart as W
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    train = K.warmstart_cases(n_train, seed=1)
+    test = K.warmstart_cases(n_test, seed=9001)
+    inits = [K.perturbed_start(c, seed=100 + i, amp=1e-4) for i, c in enumerate(train)]
+    log(f"time-to-steady: producing {n_train} training fields")
+    b, steps, status, t_data = W.run_to_steady(train, inits, tol, cap, log=log)
+    net = mlbm.Net(64, 3, K.net_init_params(64, 3, seed=3))
+    added = W.add_to_dataset(net, b, train, status)
+    b.close()
+    log("time-to-steady: training the network")
+    t0 = time.perf_counter()
+    for k, (n, lr) in enumerate([(8000, 2e-3), (6000, 5e-4), (3000, 1e-4)]):
+        loss = net.train(n, batch=4096, lr=lr, seed=k + 1)
+    t_train = time.perf_counter() - t0
+    log("time-to-steady: plain (one at a time, batched) and warm starts")
+    r = W.compare_starts(net, test, seed=500, tol=tol, max_steps=cap, sequential=True, log=log,
+                         fallback_after=60000)
+    ok = (r["plain_status"] == 0) & (r["warm_status"] == 0)
+    cells = r["cells_plain_warm"]
+    sup = (r["omega_plain"] > 0.02) & (cells[:, 0] >= 2)
+    sup[r["fallback"]] = False
+    return {
+        "tol": tol, "max_steps": cap,
+        "workload": f"{n_test} unseen ellipsoid slabs 24x4x48 (R1/d=20, R2/R1 log-uniform in [1,4], "
+                    f"De U[25,57], tau={test[0].tau}), FP64 storage; network 5-64-64-64-3 trained on "
+                    f"{added} steady fields of other cases; warm runs not converged after 60000 steps "
+                    f"fall back to the plain start",
+        "plain_sequential_s": round(r["sequential_seconds"], 3),
+        "plain_batched_s": round(r["plain_seconds"], 3),
+        "warm_batched_s": round(r["warm_seconds"], 3),
+        "inference_s": round(r["inference_seconds"], 4),
+        "steps_plain_mean": float(np.mean(r["plain_steps"])),
+        "steps_warm_mean": float(np.mean(r["warm_steps"])),
+        "supercritical_cases": int(sup.sum()),
+        "steps_plain_supercritical": int(r["plain_steps"][sup].sum()),
+        "steps_warm_supercritical": int(r["warm_steps"][sup].sum()),
+        "fallback_cases": int(len(r["fallback"])),
+        "converged_plain": int((r["plain_status"] == 0).sum()),
+        "converged_warm": int((r["warm_status"] == 0).sum()),
+        "converged_sequential": int((r["sequential_status"] == 0).sum()),
+        "max_field_diff": float(r["field_diff"][ok].max()) if ok.any() else None,
+        "cells_agree": int((cells[:, 0] == cells[:, 1]).sum()),
+        "training_data_s": round(t_data, 2), "training_s": round(t_train, 2),
+        "training_loss": float(loss),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +139,9 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="force the workgroup size (skips the autotuner)")
     ap.add_argument("--grid", type=int, default=0, help="persistent grid with --block (0: one workgroup per tile)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--steady", type=int, default=16,
+                    help="unseen cases in the time-to-steady leg (0 skips it)")
+    ap.add_argument("--steady-train", type=int, default=64, help="training fields for the warm start")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -167,10 +231,12 @@ def main():
         },
         "health": {"unstable": bad, "max_residual": max(res)},
     }
+    batch.close()
+    if args.steady > 0:
+        line["time_to_steady"] = time_to_steady(args.steady_train, args.steady)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cases[15], inits[15])
     print(json.dumps(line), flush=True)
-    batch.close()
 
 
 if __name__ == "__main__":

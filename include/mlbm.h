@@ -242,7 +242,9 @@ mlbm_status mlbm_net_adam_step(mlbm_net net, double lr);
 /* Append the cross-section nodes (theta slab 0) of a case to the device
  * training set: inputs from the description and (De, R1/d, R2/d), targets
  * from its velocity field u [3][N] (physical contravariant, e.g. from
- * mlbm_moments; host or device per on_device) over U_nom. */
+ * mlbm_moments; host or device per on_device): the physical components
+ * over U_nom, the two cross-section ones (x1, x3) multiplied by 10 so that
+ * the loss weighs the secondary flow like the streamwise profile. */
 mlbm_status mlbm_net_dataset_add(mlbm_net net, const mlbm_desc *d, double De, double R1_d, double R2_d,
                                  double U_nom, const double *u, int on_device);
 mlbm_status mlbm_net_dataset_clear(mlbm_net net);

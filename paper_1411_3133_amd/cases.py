@@ -311,6 +311,25 @@ def config4_batch(seed: int = 3133, n_pairs: int = 8, per_pair: int = 8,
 # Warm-start network: seeded initial parameters
 # --------------------------------------------------------------------------
 
+def warmstart_cases(n: int, seed: int, n1: int = 24, n3: int = 48, ratio_lo: float = 1.0,
+                    ratio_hi: float = 4.0, De_lo: float = 25.0, De_hi: float = 57.0,
+                    De_max: float = 60.0, precision: str = "f64") -> List[Case]:
+    """Warm-start study: small double-curved channels (R1/d = 20, n1 x 4 x n3)
+    with R2/R1 log-uniform in [ratio_lo, ratio_hi] and De uniform in
+    [De_lo, De_hi], one shared tau from the Mach rule at De_max.  The ratio
+    range keeps R2/d >= 20, where the scheme is stable at this tau (smaller
+    cross-sectional radii need a finer grid or a larger tau)."""
+    u = uniform_pm1(seed, 2 * n, stream=5) * 0.5 + 0.5
+    tau = round(tau_for_mach(n1, De_max, 1.0, 20.0), 4)
+    out = []
+    for i in range(n):
+        ratio = math.exp(math.log(ratio_lo) + u[2 * i] * (math.log(ratio_hi) - math.log(ratio_lo)))
+        De = float(De_lo + (De_hi - De_lo) * u[2 * i + 1])
+        out.append(ellipsoid_case(20.0, 20.0 * ratio, n1, 4, n3, tau, De=De, precision=precision,
+                                  label=f"WS{seed}-{i}"))
+    return out
+
+
 def net_shape(hidden: int, depth: int):
     """[(n_in, n_out)] per layer of the 5 -> hidden^depth -> 3 network."""
     sizes = [5] + [hidden] * depth + [3]

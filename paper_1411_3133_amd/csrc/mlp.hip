@@ -281,7 +281,14 @@ __global__ void features_kernel(CaseGeo c, float *X)
     X[p * NIN + 4] = (float)(arc / (2.0 * c.width));
 }
 
-// targets from a velocity field u [3][N] (theta slab 0), scaled by 1/U
+// The cross-section components of a steady field are 1e-3 to 1e-1 of the
+// streamwise speed; they are scaled up by SEC in the targets so that the
+// squared-error loss weighs the secondary flow comparably to the streamwise
+// profile, and scaled back in the prediction.
+constexpr double SEC = 10.0;
+
+// targets from a velocity field u [3][N] (theta slab 0): physical components
+// over U, the cross-section ones times SEC
 __global__ void targets_kernel(CaseGeo c, const double *u, double invU, float *T)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -291,9 +298,9 @@ __global__ void targets_kernel(CaseGeo c, const double *u, double invU, float *T
     node_geo(c, x1, x3, sq2, sq3, arc);
     const long N = (long)c.n1 * c.n2 * c.n3;
     const long n = ((long)x1 * c.n2) * c.n3 + x3;
-    T[p * NOUT + 0] = (float)(u[n] * invU);
+    T[p * NOUT + 0] = (float)(u[n] * invU * SEC);
     T[p * NOUT + 1] = (float)(u[N + n] * sq2 * invU);
-    T[p * NOUT + 2] = (float)(u[2 * N + n] * sq3 * invU);
+    T[p * NOUT + 2] = (float)(u[2 * N + n] * sq3 * invU * SEC);
 }
 
 // prediction -> physical contravariant velocity on every theta slab
@@ -306,9 +313,9 @@ __global__ void predict_map_kernel(CaseGeo c, const float *Y, double U, double *
     const int p = x1 * c.n3 + x3;
     double sq2, sq3, arc;
     node_geo(c, x1, x3, sq2, sq3, arc);
-    u[n] = U * Y[p * NOUT + 0];
+    u[n] = U * Y[p * NOUT + 0] / SEC;
     u[N + n] = U * Y[p * NOUT + 1] / sq2;
-    u[2 * N + n] = U * Y[p * NOUT + 2] / sq3;
+    u[2 * N + n] = U * Y[p * NOUT + 2] / (sq3 * SEC);
 }
 
 CaseGeo case_geo(const mlbm_desc &d, double De, double R1_d, double R2_d)

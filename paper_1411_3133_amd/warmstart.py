@@ -30,9 +30,10 @@ def case_params(case: K.Case):
 def run_to_steady(cases: Sequence[K.Case], inits, tol: float, max_steps: int, chunk: int = 20000,
                   log=None, stream=None):
     """Batched run to residual <= tol; returns (batch, steps, status, seconds).
-    status: 0 converged, 1 step cap, 2 unstable."""
-    b = Batch(cases, inits, stream=stream)
+    status: 0 converged, 1 step cap, 2 unstable. The time includes creating
+    the batch (geometry and initial populations)."""
     t0 = time.perf_counter()
+    b = Batch(cases, inits, stream=stream)
     n = len(cases)
     steps = np.zeros(n, np.int64)
     status = np.full(n, 1, np.int32)
@@ -76,27 +77,97 @@ def predict_inits(net: Net, cases: Sequence[K.Case]) -> List[np.ndarray]:
     return out
 
 
-def compare_starts(net: Net, cases: Sequence[K.Case], seed: int, tol: float, max_steps: int, log=None):
-    """Plain (laminar + perturbation) start vs warm start on the same cases:
-    per-instance steps to tol, wall time (inference included for the warm
-    start), and the relative L2 difference of the two converged fields."""
-    plain_init = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
+def cell_count(case: K.Case, u: np.ndarray, threshold: float = 0.1, floor: float = 1e-3) -> int:
+    """Number of secondary-flow cells: sign changes of the radial velocity
+    along x3 at mid-gap (averaged over the periodic x2 slabs), counting only
+    samples above threshold * max |u^r| so that wall layers and round-off do
+    not add cells, and none at all while max |u^r| is below floor times the
+    nominal streamwise speed (a decaying perturbation is not a cell). On a
+    periodic x3 axis the wrap-around pair of samples counts too, so each
+    vortex pair adds two."""
+    ur = u[0, case.n1 // 2].mean(axis=0)
+    m = np.abs(ur).max()
+    if not np.isfinite(m) or m < floor * K.nominal_velocity(case, case.target_De or 0.0):
+        return 0
+    s = np.sign(ur[np.abs(ur) >= threshold * m])
+    n = int(np.count_nonzero(s[1:] != s[:-1]))
+    if not case.walls & K.WALL_AXIS3 and len(s) > 1 and s[0] != s[-1]:
+        n += 1
+    return n
+
+
+def warm_start_run(net: Net, cases: Sequence[K.Case], plain_inits, tol: float, max_steps: int,
+                   fallback_after: Optional[int] = None, log=None):
+    """Batched run from the network's prediction. Instances that have not
+    reached tol after fallback_after steps are run again from their plain
+    start (the fallback) with the full max_steps, in a second batch; their
+    step count and the wall time include the abandoned warm phase. Returns (fields, steps, status,
+    seconds, inference_seconds, fallback_indices), fields[i] = (rho, u)."""
     t0 = time.perf_counter()
-    bp, sp, stp, tp = run_to_steady(cases, plain_init, tol, max_steps, log=log)
-    t1 = time.perf_counter()
     warm_init = predict_inits(net, cases)
-    t_inf = time.perf_counter() - t1
-    bw, sw, stw, tw = run_to_steady(cases, warm_init, tol, max_steps, log=log)
-    diffs = []
-    for i in range(len(cases)):
-        _, up = bp[i].moments()
-        _, uw = bw[i].moments()
-        diffs.append(float(np.linalg.norm(uw - up) / max(np.linalg.norm(up), 1e-300)))
-    init_err = []
-    for i in range(len(cases)):
-        _, up = bp[i].moments()
-        init_err.append((float(np.linalg.norm(warm_init[i] - up) / np.linalg.norm(up)),
-                         float(np.linalg.norm(plain_init[i] - up) / np.linalg.norm(up))))
-    return {"plain_steps": sp, "plain_status": stp, "plain_seconds": tp,
-            "warm_steps": sw, "warm_status": stw, "warm_seconds": tw + t_inf, "inference_seconds": t_inf,
-            "field_diff": np.array(diffs), "init_error_warm_plain": np.array(init_err)}
+    t_inf = time.perf_counter() - t0
+    budget = max_steps if fallback_after is None else min(fallback_after, max_steps)
+    bw, sw, stw, _ = run_to_steady(cases, warm_init, tol, budget, log=log)
+    fields = [bw[i].moments() for i in range(len(cases))]
+    bw.close()
+    redo = [i for i in range(len(cases)) if stw[i] != 0] if budget < max_steps else []
+    if redo:
+        if log:
+            log(f"  fallback to the plain start for {len(redo)} case(s)")
+        bf, sf, stf, _ = run_to_steady([cases[i] for i in redo], [plain_inits[i] for i in redo], tol,
+                                       max_steps, log=log)
+        for j, i in enumerate(redo):
+            sw[i] = budget + sf[j]
+            stw[i] = stf[j]
+            fields[i] = bf[j].moments()
+        bf.close()
+    return fields, sw, stw, time.perf_counter() - t0, t_inf, redo, warm_init
+
+
+def compare_starts(net: Net, cases: Sequence[K.Case], seed: int, tol: float, max_steps: int, log=None,
+                   sequential: bool = False, fallback_after: Optional[int] = None):
+    """Plain (laminar + perturbation) start vs warm start on the same cases:
+    per-instance steps to tol, wall time (inference and any fallback included
+    for the warm start), the relative L2 difference of the two converged
+    fields and their cell counts. With sequential=True the plain start is
+    also run one instance at a time (one batch of one per case)."""
+    plain_init = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
+    out = {}
+    if sequential:
+        t0 = time.perf_counter()
+        seq_steps, seq_status = [], []
+        for c, u0 in zip(cases, plain_init):
+            b1, s1, st1, _ = run_to_steady([c], [u0], tol, max_steps, stream=None)
+            seq_steps.append(int(s1[0])); seq_status.append(int(st1[0]))
+            b1.close()
+            if log:
+                log(f"  sequential case {len(seq_steps)}/{len(cases)}: steps={seq_steps[-1]} "
+                    f"status={seq_status[-1]} elapsed={time.perf_counter() - t0:.1f}s")
+        out.update(sequential_steps=np.array(seq_steps), sequential_status=np.array(seq_status),
+                   sequential_seconds=time.perf_counter() - t0)
+    bp, sp, stp, tp = run_to_steady(cases, plain_init, tol, max_steps, log=log)
+    plain_fields = [bp[i].moments() for i in range(len(cases))]
+    bp.close()
+    wf, sw, stw, tw, t_inf, redo, warm_init = warm_start_run(net, cases, plain_init, tol, max_steps,
+                                                            fallback_after, log)
+    diffs, init_err, cells = [], [], []
+    for i, c in enumerate(cases):
+        up, uw = plain_fields[i][1], wf[i][1]
+        nu = max(np.linalg.norm(up), 1e-300)
+        diffs.append(float(np.linalg.norm(uw - up) / nu))
+        init_err.append((float(np.linalg.norm(warm_init[i] - up) / nu),
+                         float(np.linalg.norm(plain_init[i] - up) / nu)))
+        cells.append((cell_count(c, up), cell_count(c, uw)))
+    out.update({"plain_steps": sp, "plain_status": stp, "plain_seconds": tp,
+                "warm_steps": sw, "warm_status": stw, "warm_seconds": tw, "inference_seconds": t_inf,
+                "fallback": np.array(redo, dtype=np.int64),
+                "field_diff": np.array(diffs), "init_error_warm_plain": np.array(init_err),
+                "cells_plain_warm": np.array(cells),
+                "omega_plain": np.array([_omega(c, plain_fields[i][1]) for i, c in enumerate(cases)])})
+    return out
+
+
+def _omega(case: K.Case, u: np.ndarray) -> float:
+    """max |u^r| at mid-gap over the nominal speed: a cheap supercriticality
+    indicator for reports (the solver's <omega> needs a live instance)."""
+    return float(np.abs(u[0, case.n1 // 2]).max() / K.nominal_velocity(case, case.target_De or 0.0))
