@@ -554,8 +554,9 @@ mlbm_status mlbm_pull_map(const mlbm_desc *d, int64_t *src_node, int32_t *src_q)
                 const int64_t n = ((int64_t)x1 * d->n2 + x2) * d->n3 + x3;
                 static_for_host<0, Q>([&](auto q) {
                     bool flip = false;
-                    const int src = fold_source<CV[q][0], CV[q][1], CV[q][2]>(h, x1, x2, x3, flip);
-                    src_node[n * Q + q] = src;
+                    int row = 0;
+                    const int col = fold_source<CV[q][0], CV[q][1], CV[q][2]>(h, x1, x2, x3, flip, row);
+                    src_node[n * Q + q] = (int64_t)row * h.P + col;
                     src_q[n * Q + q] = flip ? opposite(q) : (int)q;
                 });
             }
@@ -862,7 +863,7 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
 
 // ---------------- checkpoints ---------------------------------------------
 
-static const char CK_MAGIC[8] = {'M', 'L', 'B', 'M', 'C', 'K', '0', '1'};
+static const char CK_MAGIC[8] = {'M', 'L', 'B', 'M', 'C', 'K', '0', '2'};
 
 mlbm_status mlbm_save(mlbm_handle h, const char *path)
 {

@@ -123,7 +123,7 @@ __global__ void init_kernel(const InstDesc *dd, const double *init_u, int parity
                         + (cDc * cu - cs2 * trD * cu - 2.0 * cs2 * cDu) / (2.0 * cs2 * cs2);
         const double w = wq(q);
         const double g = w * ((rho - 1.0) + rho * (Em1 + Od));
-        dst[(size_t)q * d.N + n] = Codec<ST>::from_f64(g, w);
+        dst[pop_elem(q, x1, col, d.P)] = Codec<ST>::from_f64(g, w);
     }
 }
 
@@ -180,9 +180,10 @@ __device__ __forceinline__ void pull_f64(const InstDesc &d, int parity, int x1, 
     static_for<0, Q>([&](auto q) {
         constexpr int qo = opposite(q);
         bool flip;
-        const int n = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip);
+        int row;
+        const int col = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip, row);
         const int qs = flip ? qo : (int)q;
-        g[q] = Codec<ST>::to_f64(gload<T>(src, sizeof(T) * ((size_t)qs * d.N + n)), wq(q));
+        g[q] = Codec<ST>::to_f64(gload<T>(src, sizeof(T) * pop_elem(qs, row, col, d.P)), wq(q));
     });
 }
 
@@ -288,7 +289,8 @@ hipError_t launch_vortex(const InstDesc &h, int kind, double b, double h1, doubl
 }
 
 // ------------------------------------------------------------------------
-// Codecs: stored offsets <-> absolute FP64 populations, layout [41][N]
+// Codecs: stored offsets (row-major storage order, pop_elem) <-> absolute
+// FP64 populations in the external layout [41][N]
 // ------------------------------------------------------------------------
 
 template <int ST>
@@ -298,8 +300,9 @@ __global__ void decode_kernel(InstDesc d, int parity, double *f)
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)Q * d.N) return;
     const int q = (int)(i / d.N);
+    const int n = (int)(i - (size_t)q * d.N), x1 = n / d.P;
     const double w = wq(q);
-    f[i] = Codec<ST>::to_f64(((const T *)d.f[parity])[i], w) + w;
+    f[i] = Codec<ST>::to_f64(((const T *)d.f[parity])[pop_elem(q, x1, n - x1 * d.P, d.P)], w) + w;
 }
 
 template <int ST>
@@ -309,8 +312,9 @@ __global__ void encode_kernel(InstDesc d, int parity, const double *f)
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)Q * d.N) return;
     const int q = (int)(i / d.N);
+    const int n = (int)(i - (size_t)q * d.N), x1 = n / d.P;
     const double w = wq(q);
-    ((T *)d.f[parity])[i] = Codec<ST>::from_f64(f[i] - w, w);
+    ((T *)d.f[parity])[pop_elem(q, x1, n - x1 * d.P, d.P)] = Codec<ST>::from_f64(f[i] - w, w);
 }
 
 hipError_t launch_decode(const InstDesc &h, int st, int parity, double *f, hipStream_t s)

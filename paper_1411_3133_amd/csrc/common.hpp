@@ -82,6 +82,13 @@ __device__ __forceinline__ void gstore(void *base, uint64_t byte_off, T v)
     *(MLBM_GLOBAL T *)((MLBM_GLOBAL char *)base + byte_off) = v;
 }
 
+// Store that is not expected to be read again soon (streamed output).
+template <typename T>
+__device__ __forceinline__ void gstore_nt(void *base, uint64_t byte_off, T v)
+{
+    __builtin_nontemporal_store(v, (MLBM_GLOBAL T *)((MLBM_GLOBAL char *)base + byte_off));
+}
+
 // --- storage codecs ------------------------------------------------------
 
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t h)

@@ -347,6 +347,16 @@ constexpr int CVALS[5] = {-3, -1, 0, 1, 3};
 
 // Per-lane byte offsets of the pull sources inside an x1 row: o2[s] for the
 // theta shift -CVALS[s] (always periodic), o3[s] for the x3 shift.
+// Storage order of an instance's populations: x1 rows outermost, then the
+// 41 population planes of that row (P = n2*n3 values each, x3 fastest).
+// Element (q, x1, col) sits at (x1*Q + q)*P + col, so the 41 read and the
+// 41 write streams of a tile each lie within one block of 41*P values; with
+// planes N values apart the same streams cost about 15 % more HBM time.
+__host__ __device__ __forceinline__ uint64_t pop_elem(int q, int x1, int col, int P)
+{
+    return ((uint64_t)x1 * Q + (uint64_t)q) * (uint64_t)P + (uint64_t)col;
+}
+
 struct LaneOffsets {
     uint32_t o2[5], o3[5];
     __device__ __forceinline__ void init(int x2, int x3, int n2, int n3, bool per3, uint32_t S)
@@ -373,7 +383,7 @@ __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, 
         constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
         int r1 = x1 - c1;
         if (per1) r1 = wrap_axis(r1, d.n1);
-        const uint64_t row = ((uint64_t)q * (uint64_t)d.N + (uint64_t)r1 * (uint64_t)d.P) * S;
+        const uint64_t row = pop_elem(q, r1, 0, d.P) * S;
         const void *rowp = (const char *)src + row;
         g[q] = Codec<ST>::decode(gload<T>(rowp, L.o2[cslot(c2)] + L.o3[cslot(c3)]), (C)wq(q));
     });
@@ -384,14 +394,17 @@ __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, 
 // The backward trajectory from x along -c runs inside [-front, back]; it is
 // unfolded to y = front + 2m and folded back into [0, L], L = back + front:
 // crossings n_c = floor(y / L), every crossing reverses the velocity.
+// Returns the source column x2*n3 + x3 within the source row (written to row).
 template <int C1, int C2, int C3>
-__host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, int x2, int x3, bool &flip)
+__host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, int x2, int x3, bool &flip,
+                                                    int &row)
 {
     constexpr int a1 = C1 < 0 ? -C1 : C1, a2 = C2 < 0 ? -C2 : C2, a3 = C3 < 0 ? -C3 : C3;
     constexpr int m = a1 > a2 ? (a1 > a3 ? a1 : a3) : (a2 > a3 ? a2 : a3);
     flip = false;
     if constexpr (m == 0) {
-        return (x1 * d.n2 + x2) * d.n3 + x3;
+        row = x1;
+        return x2 * d.n3 + x3;
     } else {
         constexpr int h1 = C1 / m, h2 = C2 / m, h3 = C3 / m;
         int back = 1 << 28, front = 1 << 28;
@@ -425,7 +438,8 @@ __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, i
         if (!(d.walls & 1)) s1 = wrap_axis(s1, d.n1);
         s2 = wrap_axis(s2, d.n2);
         if (!(d.walls & 4)) s3 = wrap_axis(s3, d.n3);
-        return (s1 * d.n2 + s2) * d.n3 + s3;
+        row = s1;
+        return s2 * d.n3 + s3;
     }
 }
 
@@ -440,9 +454,11 @@ __device__ __forceinline__ void gather_general(const void *src, const InstDesc &
     static_for<0, Q>([&](auto q) {
         constexpr int qo = opposite(q);
         bool flip;
-        const int n = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip);
+        int row;
+        const int col = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip, row);
         const uint32_t qs = flip ? (uint32_t)qo : (uint32_t)q;
-        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)((qs * (uint32_t)d.N + (uint32_t)n) * S)), (C)wq(q));
+        const uint32_t e = ((uint32_t)row * (uint32_t)Q + qs) * (uint32_t)d.P + (uint32_t)col;
+        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(e * S)), (C)wq(q));
     });
 }
 

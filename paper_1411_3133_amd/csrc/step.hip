@@ -61,11 +61,11 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
             C rho, u[3];
             collide<PAT, C, typename Codec<ST>::G>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
             const size_t n = (size_t)x1 * d.P + col;
-            void *drow = (char *)dst + (uint64_t)x1 * (uint64_t)d.P * S;
+            void *drow = (char *)dst + pop_elem(0, x1, 0, d.P) * S;
             const uint32_t loff = (uint32_t)col * S;
             static_for<0, Q>([&](auto q) {
-                void *plane = (char *)drow + (uint64_t)q * (uint64_t)d.N * S;
-                gstore<T>(plane, loff, Codec<ST>::encode(g[q], (C)(1.0 / wq(q))));
+                void *plane = (char *)drow + (uint64_t)q * (uint64_t)d.P * S;
+                gstore_nt<T>(plane, loff, Codec<ST>::encode(g[q], (C)(1.0 / wq(q))));
             });
             if constexpr (CHECK) {
                 double *us = d.usnap;
