@@ -158,8 +158,8 @@ mlbm_status ensure_scratch(Batch *B, size_t bytes)
 
 void destroy_graph(Batch *B)
 {
-    if (B->graph) hipGraphExecDestroy(B->graph);
-    if (B->graph_src) hipGraphDestroy(B->graph_src);
+    if (B->graph) (void)hipGraphExecDestroy(B->graph);
+    if (B->graph_src) (void)hipGraphDestroy(B->graph_src);
     B->graph = nullptr;
     B->graph_src = nullptr;
     B->graph_valid = false;
@@ -232,7 +232,7 @@ mlbm_status capture_window(Batch *B)
     B->t = t0;
     for (size_t i = 0; i < B->inst.size(); ++i) B->inst[i].t = it0[i];
     if (st != MLBM_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return st;
     }
     HIP_TRY(e);
@@ -300,7 +300,7 @@ GeoEntry *find_or_make_geo(Batch *B, const mlbm_desc &d, int &key, mlbm_status &
     scales(d, p.dt, p.s);
     e = launch_geometry(g.ptr, p, B->stream);
     if (e != hipSuccess) {
-        hipFree(g.ptr);
+        (void)hipFree(g.ptr);
         st = fail(MLBM_E_HIP, std::string("geometry kernel: ") + hipGetErrorString(e));
         return nullptr;
     }
@@ -313,26 +313,26 @@ GeoEntry *find_or_make_geo(Batch *B, const mlbm_desc &d, int &key, mlbm_status &
 void free_batch(Batch *B)
 {
     if (!B) return;
-    if (B->stream) hipStreamSynchronize(B->stream);
+    if (B->stream) (void)hipStreamSynchronize(B->stream);
     destroy_graph(B);
     for (auto &I : B->inst) {
-        if (I.hd.f[0]) hipFree(I.hd.f[0]);
-        if (I.hd.f[1]) hipFree(I.hd.f[1]);
-        if (I.hd.usnap) hipFree(I.hd.usnap);
+        if (I.hd.f[0]) (void)hipFree(I.hd.f[0]);
+        if (I.hd.f[1]) (void)hipFree(I.hd.f[1]);
+        if (I.hd.usnap) (void)hipFree(I.hd.usnap);
     }
     for (auto &g : B->geos)
-        if (g.ptr) hipFree(g.ptr);
-    if (B->d_insts) hipFree(B->d_insts);
-    if (B->d_tiles) hipFree(B->d_tiles);
-    if (B->d_ntiles) hipFree(B->d_ntiles);
-    if (B->d_partials) hipFree(B->d_partials);
-    if (B->d_pb) hipFree(B->d_pb);
-    if (B->d_pc) hipFree(B->d_pc);
-    if (B->d_ws) hipFree(B->d_ws);
-    if (B->d_scratch) hipFree(B->d_scratch);
-    if (B->ev0) hipEventDestroy(B->ev0);
-    if (B->ev1) hipEventDestroy(B->ev1);
-    if (B->own_stream && B->stream) hipStreamDestroy(B->stream);
+        if (g.ptr) (void)hipFree(g.ptr);
+    if (B->d_insts) (void)hipFree(B->d_insts);
+    if (B->d_tiles) (void)hipFree(B->d_tiles);
+    if (B->d_ntiles) (void)hipFree(B->d_ntiles);
+    if (B->d_partials) (void)hipFree(B->d_partials);
+    if (B->d_pb) (void)hipFree(B->d_pb);
+    if (B->d_pc) (void)hipFree(B->d_pc);
+    if (B->d_ws) (void)hipFree(B->d_ws);
+    if (B->d_scratch) (void)hipFree(B->d_scratch);
+    if (B->ev0) (void)hipEventDestroy(B->ev0);
+    if (B->ev1) (void)hipEventDestroy(B->ev1);
+    if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
     delete B;
 }
 
@@ -356,8 +356,11 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
     B->K = K;
     B->pat = pat;
     int dev = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&B->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&B->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        delete B;
+        return fail(MLBM_E_HIP, "no HIP device");
+    }
     if (stream) {
         B->stream = (hipStream_t)stream;
     } else {
@@ -418,13 +421,13 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
             const size_t bytes = sizeof(double) * 3 * (size_t)I.hd.N;
             if (hipMalloc(&du, bytes) != hipSuccess) return bail(fail(MLBM_E_OOM, "init_u staging failed"));
             if (hipMemcpyAsync(du, ds[i].init_u, bytes, hipMemcpyHostToDevice, B->stream) != hipSuccess) {
-                hipFree(du);
+                (void)hipFree(du);
                 return bail(fail(MLBM_E_HIP, "init_u upload failed"));
             }
         }
         hipError_t e = launch_init(B->d_insts + i, I.hd, B->st, du, 0, B->stream);
-        hipStreamSynchronize(B->stream);
-        if (du) hipFree(du);
+        (void)hipStreamSynchronize(B->stream);
+        if (du) (void)hipFree(du);
         if (e != hipSuccess) return bail(fail(MLBM_E_HIP, std::string("init kernel: ") + hipGetErrorString(e)));
     }
     if (hipStreamSynchronize(B->stream) != hipSuccess) return bail(fail(MLBM_E_HIP, "initialisation failed"));
@@ -825,15 +828,15 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
             }
             float cand = 1e30f;
             for (int rep = 0; rep < 3; ++rep) {
-                hipEventRecord(B->ev0, B->stream);
+                if (hipEventRecord(B->ev0, B->stream) != hipSuccess) st = MLBM_E_HIP;
                 for (int k = 0; k < steps; ++k) {
                     a.parity = (int)((t_keep + k) & 1);
                     if (launch_step(a, B->pat, B->st, false, launch_grid(B), B->block, B->stream) != hipSuccess) st = MLBM_E_HIP;
                 }
-                hipEventRecord(B->ev1, B->stream);
-                hipEventSynchronize(B->ev1);
                 float ms = 0.0f;
-                hipEventElapsedTime(&ms, B->ev0, B->ev1);
+                if (hipEventRecord(B->ev1, B->stream) != hipSuccess || hipEventSynchronize(B->ev1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, B->ev0, B->ev1) != hipSuccess)
+                    st = MLBM_E_HIP;
                 cand = std::min(cand, ms);
             }
             if (cand < best) { best = cand; bb = blocks[ib]; bg = grids[ig]; }
@@ -843,16 +846,17 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
         if (!backup[i]) continue;
         Instance &I = B->inst[i];
         const size_t bytes = sb * Q * (size_t)I.hd.N;
-        hipMemcpyAsync(I.hd.f[parity_of(I)], backup[i], bytes, hipMemcpyDeviceToDevice, B->stream);
+        if (hipMemcpyAsync(I.hd.f[parity_of(I)], backup[i], bytes, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
+            st = MLBM_E_HIP;
     }
-    hipStreamSynchronize(B->stream);
+    if (hipStreamSynchronize(B->stream) != hipSuccess) st = MLBM_E_HIP;
     for (void *p : backup)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     if (st != MLBM_OK) {
         B->block = old_block;
         B->grid = old_grid;
-        build_tiles(B);
-        return fail(st, "autotune launch failed");
+        (void)build_tiles(B);
+        return fail(st, "autotune launch, timing or state restore failed");
     }
     B->block = bb;
     B->grid = bg;

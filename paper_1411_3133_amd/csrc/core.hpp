@@ -335,10 +335,20 @@ __device__ __forceinline__ void moments_only(const C (&g)[Q], C &rho_out, C (&u_
 // Streaming
 // ------------------------------------------------------------------------
 
+// Periodic wrap of a coordinate shifted by at most 3 cells, v in [-3, n + 2]
+// (every pull, including the folded ones: a wall-reflected source lies at
+// most 3 cells along each axis from the node). One correction each way is
+// exact for n >= 3; axes of 1 or 2 nodes take two more.
 __host__ __device__ __forceinline__ int wrap_axis(int v, int n)
 {
-    while (v < 0) v += n;
-    while (v >= n) v -= n;
+    v += v < 0 ? n : 0;
+    v -= v >= n ? n : 0;
+    if (n < 3) {
+        v += v < 0 ? n : 0;
+        v += v < 0 ? n : 0;
+        v -= v >= n ? n : 0;
+        v -= v >= n ? n : 0;
+    }
     return v;
 }
 
@@ -379,13 +389,74 @@ __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, 
     using C = typename Codec<ST>::C;
     constexpr uint64_t S = sizeof(T);
     const bool per1 = !(d.walls & 1);
+    const uint64_t PS = (uint64_t)d.P * S;
+    uint64_t rb[5];   // byte offset of plane 0 of the source row x1 - CVALS[s]
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        int r1 = x1 - CVALS[k];
+        if (per1) r1 = wrap_axis(r1, d.n1);
+        rb[k] = (uint64_t)r1 * (uint64_t)Q * PS;
+    }
     static_for<0, Q>([&](auto q) {
         constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
-        int r1 = x1 - c1;
-        if (per1) r1 = wrap_axis(r1, d.n1);
-        const uint64_t row = pop_elem(q, r1, 0, d.P) * S;
-        const void *rowp = (const char *)src + row;
+        const void *rowp = (const char *)src + rb[cslot(c1)] + (uint64_t)q * PS;
         g[q] = Codec<ST>::decode(gload<T>(rowp, L.o2[cslot(c2)] + L.o3[cslot(c3)]), (C)wq(q));
+    });
+}
+
+// Pull for a wavefront whose x1 row is out of reach of x1 walls while some
+// of its lanes are within reach of an x3 wall (x3 walled, n3 >= 5). Only the
+// x3 wall can then be met, and at most once: a population with c3 != 0 whose
+// backward path from x meets the wall behind it (dist = x3 or n3 - 1 - x3
+// nodes; a crossing when 2 dist + 1 < 2m, m = max |c_a|) comes from the
+// opposite population at x - (c/m) sb with sb = 2 dist + 1 - m, the
+// single-reflection case of fold_source below. Every other population is
+// the plain pull. Candidates are formed from per-wave row offsets and
+// per-lane in-row offsets and chosen per lane by selects, so the path has
+// no branches; byte offsets fit in 32 bits (buffers are below 4 GiB).
+template <int ST>
+__device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d, int x1, int x2, int x3,
+                                              const LaneOffsets &L, typename Codec<ST>::G (&g)[Q])
+{
+    using T = typename Codec<ST>::T;
+    using C = typename Codec<ST>::C;
+    constexpr uint32_t S = sizeof(T);
+    const bool per1 = !(d.walls & 1);
+    const uint32_t PS = (uint32_t)d.P * S;
+    uint32_t rb[7];   // byte offset of plane 0 of the source row x1 - t, t = -3..3
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        int r1 = x1 - (k - 3);
+        if (per1) r1 = wrap_axis(r1, d.n1);
+        rb[k] = (uint32_t)r1 * (uint32_t)Q * PS;
+    }
+    const uint32_t n3S = (uint32_t)d.n3 * S;
+    // in-row x2 offsets of x2 - t for t = -3..3
+    const uint32_t o2t[7] = {L.o2[0], (uint32_t)wrap_axis(x2 + 2, d.n2) * n3S, L.o2[1], L.o2[2], L.o2[3],
+                             (uint32_t)wrap_axis(x2 - 2, d.n2) * n3S, L.o2[4]};
+    const uint32_t x3S = (uint32_t)x3 * S;
+    const int dlo = x3, dhi = d.n3 - 1 - x3;
+    static_for<0, Q>([&](auto q) {
+        constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
+        constexpr int a1 = c1 < 0 ? -c1 : c1, a2 = c2 < 0 ? -c2 : c2, a3 = c3 < 0 ? -c3 : c3;
+        constexpr int m = a1 > a2 ? (a1 > a3 ? a1 : a3) : (a2 > a3 ? a2 : a3);
+        uint32_t off = rb[3 + c1] + (uint32_t)q * PS + L.o2[cslot(c2)] + L.o3[cslot(c3)];
+        if constexpr (c3 != 0) {
+            constexpr int qo = opposite(q);
+            constexpr int h1 = c1 / m, h2 = c2 / m, h3 = c3 / m;
+            const int dist = c3 > 0 ? dlo : dhi;
+            const uint32_t base = (uint32_t)qo * PS;
+            if constexpr (m == 1) {
+                const uint32_t o0 = rb[3] + base + L.o2[2] + x3S;            // sb = 0: the node itself
+                off = dist == 0 ? o0 : off;
+            } else {
+                const uint32_t oa = rb[3 - 2 * h1] + base + o2t[3 - 2 * h2] + (uint32_t)((int)x3S + 2 * h3 * (int)S);
+                const uint32_t ob = rb[3] + base + L.o2[2] + x3S;
+                const uint32_t oc = rb[3 + 2 * h1] + base + o2t[3 + 2 * h2] + (uint32_t)((int)x3S - 2 * h3 * (int)S);
+                off = dist == 0 ? oa : (dist == 1 ? ob : (dist == 2 ? oc : off));
+            }
+        }
+        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)off), (C)wq(q));
     });
 }
 

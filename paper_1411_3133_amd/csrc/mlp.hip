@@ -361,7 +361,7 @@ hipError_t dispatch_H(int H, F &&f)
 mlbm_status ensure_batch(mlbm_net_s *N, int64_t n)
 {
     if (n <= N->bcap) return MLBM_OK;
-    hipFree(N->Y); hipFree(N->hid); hipFree(N->dl); hipFree(N->part); hipFree(N->sel); hipFree(N->lossp);
+    (void)hipFree(N->Y); (void)hipFree(N->hid); (void)hipFree(N->dl); (void)hipFree(N->part); (void)hipFree(N->sel); (void)hipFree(N->lossp);
     const int H = N->sh.H, D = N->sh.depth;
     const int64_t nch = (n + CHUNK - 1) / CHUNK;
     NET_TRY(hipMalloc(&N->Y, sizeof(float) * NOUT * n));
@@ -448,11 +448,11 @@ mlbm_status mlbm_net_create(int hidden, int depth, const double *init_params, vo
 void mlbm_net_destroy(mlbm_net N)
 {
     if (!N) return;
-    if (N->stream) hipStreamSynchronize(N->stream);
-    hipFree(N->p); hipFree(N->m); hipFree(N->v); hipFree(N->g);
-    hipFree(N->X); hipFree(N->T);
-    hipFree(N->Y); hipFree(N->hid); hipFree(N->dl); hipFree(N->part); hipFree(N->sel); hipFree(N->lossp);
-    if (N->own_stream) hipStreamDestroy(N->stream);
+    if (N->stream) (void)hipStreamSynchronize(N->stream);
+    (void)hipFree(N->p); (void)hipFree(N->m); (void)hipFree(N->v); (void)hipFree(N->g);
+    (void)hipFree(N->X); (void)hipFree(N->T);
+    (void)hipFree(N->Y); (void)hipFree(N->hid); (void)hipFree(N->dl); (void)hipFree(N->part); (void)hipFree(N->sel); (void)hipFree(N->lossp);
+    if (N->own_stream) (void)hipStreamDestroy(N->stream);
     delete N;
 }
 
@@ -491,7 +491,7 @@ mlbm_status mlbm_net_forward(mlbm_net N, const float *x, int64_t n, float *y)
     });
     if (e == hipSuccess) e = hipMemcpyAsync(y, N->Y, sizeof(float) * NOUT * n, hipMemcpyDeviceToHost, N->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(N->stream);
-    hipFree(dx);
+    (void)hipFree(dx);
     NET_TRY(e);
     return MLBM_OK;
 }
@@ -512,9 +512,9 @@ mlbm_status mlbm_net_gradient(mlbm_net N, const float *x, const float *t, int64_
         if (e != hipSuccess) st = nfail(MLBM_E_HIP, hipGetErrorString(e));
         for (long k = 0; k < N->sh.np; ++k) grad[k] = h[k];
     }
-    hipStreamSynchronize(N->stream);
-    hipFree(dx);
-    hipFree(dt);
+    (void)hipStreamSynchronize(N->stream);
+    (void)hipFree(dx);
+    (void)hipFree(dt);
     return st;
 }
 
@@ -543,8 +543,8 @@ mlbm_status mlbm_net_dataset_add(mlbm_net N, const mlbm_desc *d, double De, doub
             NET_TRY(hipMemcpyAsync(T, N->T, sizeof(float) * NOUT * N->M, hipMemcpyDeviceToDevice, N->stream));
             NET_TRY(hipStreamSynchronize(N->stream));
         }
-        hipFree(N->X);
-        hipFree(N->T);
+        (void)hipFree(N->X);
+        (void)hipFree(N->T);
         N->X = X;
         N->T = T;
         N->cap = cap;
@@ -562,7 +562,7 @@ mlbm_status mlbm_net_dataset_add(mlbm_net N, const mlbm_desc *d, double De, doub
                        N->T + NOUT * N->M);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(N->stream);
-    if (tmp) hipFree(tmp);
+    if (tmp) (void)hipFree(tmp);
     NET_TRY(e);
     N->M += P;
     return MLBM_OK;
@@ -640,8 +640,8 @@ mlbm_status mlbm_warmstart_predict(mlbm_net N, const mlbm_desc *d, double De, do
     if (e == hipSuccess && !on_device)
         e = hipMemcpyAsync(u_out, du, sizeof(double) * 3 * N3, hipMemcpyDeviceToHost, N->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(N->stream);
-    hipFree(X);
-    if (du) hipFree(du);
+    (void)hipFree(X);
+    if (du) (void)hipFree(du);
     NET_TRY(e);
     return MLBM_OK;
 }

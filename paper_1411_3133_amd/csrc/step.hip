@@ -5,7 +5,9 @@
 // wavefront, the choice between the plain pull and the bounce-back pull,
 // the source row x1 - c1 and the geometry of x3-independent cases are
 // scalar; only the in-row offset of a pull is per lane, so the 41 loads of a
-// node are coalesced runs along x3.  The launch is persistent: workgroups
+// node are coalesced runs along x3. Wavefronts next to an x3 wall take a
+// branch-free variant that resolves the single x3 reflection per lane;
+// rows next to an x1 wall take the general fold.  The launch is persistent: workgroups
 // stride over the flat tile queue of all active instances, and the number
 // of queued tiles is read from device memory so that a captured graph stays
 // valid when instances retire.
@@ -43,15 +45,19 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
 
         const bool wall1_row = (d.walls & 1) && (x1 < 3 || x1 > d.n1 - 4);
         const bool near3 = valid && (d.walls & 4) && (x3 < 3 || x3 > d.n3 - 4);
-        const bool general = wall1_row || (__ballot(near3) != 0);
+        const bool any3 = __ballot(near3) != 0;
 
         double dsq = 0.0, usq = 0.0, badf = 0.0;
         if (valid) {
             typename Codec<ST>::G g[Q];
-            if (!general) {
+            if (!wall1_row && !any3) {
                 LaneOffsets L;
                 L.init(x2, x3, d.n2, d.n3, !(d.walls & 4), S);
                 gather_fast<ST>(src, d, x1, L, g);
+            } else if (!wall1_row && d.n3 >= 5) {
+                LaneOffsets L;
+                L.init(x2, x3, d.n2, d.n3, false, S);
+                gather_x3wall<ST>(src, d, x1, x2, x3, L, g);
             } else {
                 gather_general<ST>(src, d, x1, x2, x3, g);
             }

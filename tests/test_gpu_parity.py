@@ -41,6 +41,14 @@ TINY = [
     ("cyl-old", K.cylinder_case(0.8, 8, 2, 6, 0.8, De=10.0, forcing_mode=1)),
     ("ell", K.ellipsoid_case(20.0, 5.0, 12, 2, 16, 0.6, De=5.0)),
     ("ell-wide", K.ellipsoid_case(20.0, 40.0, 8, 3, 70, 0.7, De=5.0)),
+    # x3 walls only, periodic x1: every row takes the x3-wall gather
+    ("flat-w3", K.Case(kind="flat", n1=5, n2=3, n3=7, walls=4, width=1.0, tau=0.7, force=2e-3)),
+    # smallest walled x3 of the x3-wall gather: the 2-cell reflections meet both walls
+    ("flat-w3-n5", K.Case(kind="flat", n1=4, n2=2, n3=5, walls=4, width=1.0, tau=0.75, force=2e-3)),
+    # walled x3 of 4 nodes: multiple reflections, handled by the general fold
+    ("flat-w3-n4", K.Case(kind="flat", n1=4, n2=2, n3=4, walls=4, width=1.0, tau=0.75, force=2e-3)),
+    # interior rows with wall-crossing and interior lanes in the same wavefronts
+    ("cyl-w13-wide", K.cylinder_case(0.9, 10, 3, 70, 0.75, De=10.0, walls3=True)),
 ]
 
 
