@@ -460,6 +460,55 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
     });
 }
 
+// Pull for a wavefront in a row within reach of an x1 wall while none of its
+// lanes is within reach of an x3 wall. x1 is uniform across the wavefront,
+// so whether a population meets the x1 wall behind it (back = 2 x1 + 1 or
+// 2 n1 - 1 - 2 x1 half-cells, a crossing when back < 2m) and its step count
+// sb = back - m are scalars: the source row and plane are uniform and only
+// the in-row offset of x - (c/m) sb varies per lane. One x1 crossing at
+// most (a single walled axis of >= 4 nodes), as in fold_source below.
+template <int ST>
+__device__ __forceinline__ void gather_x1wall(const void *src, const InstDesc &d, int x1, int x2, int x3,
+                                              const LaneOffsets &L, typename Codec<ST>::G (&g)[Q])
+{
+    using T = typename Codec<ST>::T;
+    using C = typename Codec<ST>::C;
+    constexpr uint32_t S = sizeof(T);
+    const bool per3 = !(d.walls & 4);
+    const uint32_t PS = (uint32_t)d.P * S;
+    const uint32_t n3S = (uint32_t)d.n3 * S;
+    // in-row offsets of x - t along x2 and x3 for t = -2, 0, 2 (index 0, 1, 2)
+    const uint32_t o2s[3] = {(uint32_t)wrap_axis(x2 + 2, d.n2) * n3S, L.o2[2], (uint32_t)wrap_axis(x2 - 2, d.n2) * n3S};
+    const uint32_t o3s[3] = {(uint32_t)(per3 ? wrap_axis(x3 + 2, d.n3) : x3 + 2) * S, L.o3[2],
+                             (uint32_t)(per3 ? wrap_axis(x3 - 2, d.n3) : x3 - 2) * S};
+    const int lo = 2 * x1 + 1, hi = 2 * d.n1 - 1 - 2 * x1;
+    static_for<0, Q>([&](auto q) {
+        constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
+        constexpr int a1 = c1 < 0 ? -c1 : c1, a2 = c2 < 0 ? -c2 : c2, a3 = c3 < 0 ? -c3 : c3;
+        constexpr int m = a1 > a2 ? (a1 > a3 ? a1 : a3) : (a2 > a3 ? a2 : a3);
+        uint32_t rowoff, inrow;
+        if constexpr (c1 == 0) {
+            rowoff = ((uint32_t)x1 * (uint32_t)Q + (uint32_t)q) * PS;
+            inrow = L.o2[cslot(c2)] + L.o3[cslot(c3)];
+        } else {
+            constexpr int qo = opposite(q);
+            constexpr int h1 = c1 / m, h2 = c2 / m, h3 = c3 / m;
+            const int back = c1 > 0 ? lo : hi;
+            if (back >= 2 * m) {                        // no crossing: the plain pull
+                rowoff = ((uint32_t)(x1 - c1) * (uint32_t)Q + (uint32_t)q) * PS;
+                inrow = L.o2[cslot(c2)] + L.o3[cslot(c3)];
+            } else {                                    // reflected: plane qo at x - (c/m) sb
+                const int sb = back - m;                // -2, 0 or 2 (m = 3), 0 (m = 1)
+                rowoff = ((uint32_t)(x1 - h1 * sb) * (uint32_t)Q + (uint32_t)qo) * PS;
+                const int k = sb == 0 ? 1 : (sb > 0 ? 2 : 0);   // index of t = sb
+                const int k2 = h2 == 0 ? 1 : (h2 > 0 ? k : 2 - k), k3 = h3 == 0 ? 1 : (h3 > 0 ? k : 2 - k);
+                inrow = (k2 == 0 ? o2s[0] : (k2 == 1 ? o2s[1] : o2s[2])) + (k3 == 0 ? o3s[0] : (k3 == 1 ? o3s[1] : o3s[2]));
+            }
+        }
+        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(rowoff + inrow)), (C)wq(q));
+    });
+}
+
 // Source of a pull when a wall may be within reach.  Ticks of 1/(2m) step
 // (m = max |c_a|) put the walls at odd and the nodes at even tick counts.
 // The backward trajectory from x along -c runs inside [-front, back]; it is

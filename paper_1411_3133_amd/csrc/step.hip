@@ -6,8 +6,9 @@
 // the source row x1 - c1 and the geometry of x3-independent cases are
 // scalar; only the in-row offset of a pull is per lane, so the 41 loads of a
 // node are coalesced runs along x3. Wavefronts next to an x3 wall take a
-// branch-free variant that resolves the single x3 reflection per lane;
-// rows next to an x1 wall take the general fold.  The launch is persistent: workgroups
+// branch-free variant that resolves the single x3 reflection per lane, rows
+// next to an x1 wall one whose reflections are uniform per wavefront;
+// wavefronts at a corner of both take the general fold.  The launch is persistent: workgroups
 // stride over the flat tile queue of all active instances, and the number
 // of queued tiles is read from device memory so that a captured graph stays
 // valid when instances retire.
@@ -58,6 +59,10 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
                 LaneOffsets L;
                 L.init(x2, x3, d.n2, d.n3, false, S);
                 gather_x3wall<ST>(src, d, x1, x2, x3, L, g);
+            } else if (!any3) {
+                LaneOffsets L;
+                L.init(x2, x3, d.n2, d.n3, !(d.walls & 4), S);
+                gather_x1wall<ST>(src, d, x1, x2, x3, L, g);
             } else {
                 gather_general<ST>(src, d, x1, x2, x3, g);
             }

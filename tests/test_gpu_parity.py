@@ -47,8 +47,9 @@ TINY = [
     ("flat-w3-n5", K.Case(kind="flat", n1=4, n2=2, n3=5, walls=4, width=1.0, tau=0.75, force=2e-3)),
     # walled x3 of 4 nodes: multiple reflections, handled by the general fold
     ("flat-w3-n4", K.Case(kind="flat", n1=4, n2=2, n3=4, walls=4, width=1.0, tau=0.75, force=2e-3)),
-    # interior rows with wall-crossing and interior lanes in the same wavefronts
-    ("cyl-w13-wide", K.cylinder_case(0.9, 10, 3, 70, 0.75, De=10.0, walls3=True)),
+    # wall-crossing and interior lanes in the same wavefronts, and x1-wall rows
+    # with wavefronts clear of the x3 walls (x3 gather, x1 gather, corners)
+    ("cyl-w13-wide", K.cylinder_case(0.9, 10, 2, 140, 0.75, De=10.0, walls3=True)),
 ]
 
 
