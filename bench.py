@@ -129,6 +129,50 @@ def time_to_steady(n_train, n_test, tol=1e-6, cap=150000):
     }
 
 
+def critical_dean_leg(tol=1e-7):
+    """Critical Dean numbers (onset of 2, 4 and 6 cells) of the stable
+    curvature pairs of the batched sweep, at N_r = 32, by batched bisection to
+    1 % brackets: once from plain starts, once warm-started by a network
+    trained on the sweep's own first-round fields. Reports both and their
+    largest relative difference (measured De, bracket midpoints)."""
+    from paper_1411_3133_amd import cases as K
+    from paper_1411_3133_amd import sweep
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    pairs = K.critical_pairs()
+    grid = [20.0 + 5.0 * i for i in range(13)]
+    res = {}
+    for warm in (False, True):
+        log(f"critical De: {'warm' if warm else 'plain'} starts")
+        res[warm] = sweep.critical_dean(pairs, grid, tol=tol, max_steps=400000, warm=warm, log=log)
+
+    def mid(x):
+        return None if None in x else 0.5 * (x[0] + x[1])
+
+    onsets, diffs = {}, []
+    for key, a in res[False]["onsets"].items():
+        b = res[True]["onsets"][key]
+        ma, mb = mid(a["De_measured"]), mid(b["De_measured"])
+        if ma is None and mb is None:
+            continue
+        onsets[key] = [None if ma is None else round(ma, 3), None if mb is None else round(mb, 3)]
+        if ma is not None and mb is not None:
+            diffs.append(abs(ma - mb) / ma)
+    return {
+        "workload": f"{len(pairs)} curvature pairs of the batched sweep (R2/d >= 18), ellipsoid slabs 32x4xn3, "
+                    f"De grid 20..80 then bisection to 1 % brackets, FP64, residual {tol:g}",
+        "onsets_plain_warm": onsets,
+        "max_rel_diff": round(max(diffs), 5) if diffs else None,
+        "within_1pct": f"{sum(d <= 0.01 for d in diffs)}/{len(diffs)}",
+        "seconds_plain": res[False]["seconds"], "seconds_warm": res[True]["seconds"],
+        "train_seconds": res[True]["train_seconds"],
+        "instance_steps_plain": sum(r["instance_steps"] for r in res[False]["rounds"]),
+        "instance_steps_warm": sum(r["instance_steps"] for r in res[True]["rounds"]),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +186,7 @@ def main():
     ap.add_argument("--steady", type=int, default=16,
                     help="unseen cases in the time-to-steady leg (0 skips it)")
     ap.add_argument("--steady-train", type=int, default=64, help="training fields for the warm start")
+    ap.add_argument("--critical", type=int, default=1, help="run the critical-De leg (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -234,6 +279,8 @@ def main():
     batch.close()
     if args.steady > 0:
         line["time_to_steady"] = time_to_steady(args.steady_train, args.steady)
+    if args.critical:
+        line["critical_dean"] = critical_dean_leg()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cases[15], inits[15])
     print(json.dumps(line), flush=True)

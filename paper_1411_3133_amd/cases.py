@@ -330,6 +330,32 @@ def warmstart_cases(n: int, seed: int, n1: int = 24, n3: int = 48, ratio_lo: flo
     return out
 
 
+def critical_pairs(seed: int = 3133, n1: int = 32, De_max: float = 80.0, min_R2: float = 18.0,
+                   precision: str = "f64", n_pairs: int = 8):
+    """Curvature pairs of the batched sweep (config4_batch with the same
+    seed) for the critical-De study: pairs with R2/d >= min_R2 (the scheme's
+    stable range at this tau), each at n1 x 4 x n3 with the pair's
+    cross-section aspect n3/n1 kept (n3 rounded to a multiple of 4, >= 8),
+    one tau from the Mach rule at De_max. Returns [(label, make(De) -> Case)]."""
+    u = uniform_pm1(seed, 4 * n_pairs + n_pairs * 8, stream=4) * 0.5 + 0.5
+    tau = round(tau_for_mach(n1, De_max, 1.0, 20.0), 4)
+    out = []
+    for p in range(n_pairs):
+        ratio = math.exp(math.log(0.25) + u[4 * p] * (math.log(4.0) - math.log(0.25)))
+        R2 = 20.0 * ratio
+        if R2 < min_R2:
+            continue
+        n1_c4 = 32 + int(u[4 * p + 1] * 65)
+        n3_c4 = max(16, ((64 + int(u[4 * p + 2] * 193)) // 16) * 16)
+        n3 = max(8, int(round(n3_c4 * n1 / n1_c4 / 4.0)) * 4)
+
+        def make(De, R2=R2, n3=n3, p=p):
+            return ellipsoid_case(20.0, R2, n1, 4, n3, tau, De=float(De), precision=precision,
+                                  label=f"C4-p{p}")
+        out.append((f"C4-p{p}", make))
+    return out
+
+
 def net_shape(hidden: int, depth: int):
     """[(n_in, n_out)] per layer of the 5 -> hidden^depth -> 3 network."""
     sizes = [5] + [hidden] * depth + [3]

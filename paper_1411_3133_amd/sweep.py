@@ -1,0 +1,111 @@
+"""Critical Dean numbers of curvature pairs by batched bisection.
+
+The onset of k secondary-flow cells (k = 2, 4, 6) of a curvature pair is the
+smallest De whose steady state shows at least k cells (cell counting: see
+warmstart.cell_count). Round 0 runs a grid of De values of every pair in one
+batch; every later round runs the midpoints of all open brackets in one
+batch, until each bracket is narrower than `rel_width` of its upper end.
+Runs start from the laminar profile with a seeded 1e-4 perturbation, or from
+the warm-start network trained on the round-0 fields (plain start as
+fallback). Orchestration only: every step runs in libmlbm's kernels.
+"""
+from __future__ import annotations
+
+import time
+from typing import Callable, Dict, List, Sequence, Tuple
+
+import numpy as np
+
+from . import cases as K
+from . import warmstart as W
+from .mlbm import Net
+
+
+def _run(cases, inits_plain, tol, max_steps, net=None, fallback_after=None, log=None):
+    """Fields, steps, status and measured De of a batch of cases."""
+    if net is None:
+        b, steps, status, secs = W.run_to_steady(cases, inits_plain, tol, max_steps, log=log)
+        fields = [b[i].moments() for i in range(len(cases))]
+        De = np.array([b[i].vortex_intensity()[2] for i in range(len(cases))])
+        b.close()
+        return fields, steps, status, De, secs
+    fields, steps, status, secs, _, _, _, obs = W.warm_start_run(net, cases, inits_plain, tol, max_steps,
+                                                                 fallback_after, log)
+    return fields, steps, status, np.array([o[2] for o in obs]), secs
+
+
+def critical_dean(pairs: Sequence[Tuple[str, Callable[[float], K.Case]]], De_grid: Sequence[float],
+                  ks: Sequence[int] = (2, 4, 6), rel_width: float = 0.01, tol: float = 1e-6,
+                  max_steps: int = 200000, seed: int = 7, warm: bool = False, net_shape=(64, 3),
+                  train_steps=((8000, 2e-3), (6000, 5e-4), (3000, 1e-4)), fallback_after: int = 60000,
+                  log=None) -> Dict:
+    """Bracket the onset De of k cells for every pair; returns brackets of
+    nominal and measured De per (pair, k), the cell counts seen, and wall
+    time and instance-steps per round."""
+    t_all = time.perf_counter()
+    seen: Dict[Tuple[str, float], Tuple[int, float, int]] = {}   # (pair, De_nom) -> (cells, De_meas, status)
+    rounds = []
+
+    def run_round(items, net=None):
+        cases = [make(De) for (_, make, De) in items]
+        plain = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
+        fields, steps, status, De_meas, secs = _run(cases, plain, tol, max_steps, net, fallback_after, log)
+        for (name, _, De), c, (_, u), st, dm in zip(items, cases, fields, status, De_meas):
+            seen[(name, De)] = (W.cell_count(c, u), float(dm), int(st))
+        rounds.append({"instances": len(items), "seconds": round(secs, 3), "instance_steps": int(np.sum(steps)),
+                       "converged": int(np.sum(status == 0)), "unstable": int(np.sum(status == 2))})
+        return cases, fields, status
+
+    grid = [(name, make, float(De)) for name, make in pairs for De in De_grid]
+    cases0, fields0, status0 = run_round(grid)
+    net = None
+    t_train = 0.0
+    if warm:
+        t0 = time.perf_counter()
+        net = Net(net_shape[0], net_shape[1], K.net_init_params(net_shape[0], net_shape[1], seed=3))
+        for c, (_, u), st in zip(cases0, fields0, status0):
+            if st == 0 and np.all(np.isfinite(u)):
+                De, R1, R2, U = W.case_params(c)
+                net.dataset_add(c, u, De, R1, R2, U)
+        for k, (n, lr) in enumerate(train_steps):
+            net.train(n, batch=4096, lr=lr, seed=k + 1)
+        t_train = time.perf_counter() - t0
+
+    def bracket(name, k):
+        des = sorted(De for (n, De) in seen if n == name)
+        cells = [seen[(name, De)][0] for De in des]
+        for i, c in enumerate(cells):
+            if c >= k:
+                return (des[i - 1], des[i]) if i > 0 else (None, des[i])
+        return (des[-1], None)
+
+    makers = dict(pairs)
+    while True:
+        todo = {}
+        for name, _ in pairs:
+            for k in ks:
+                lo, hi = bracket(name, k)
+                if lo is None or hi is None or (hi - lo) <= rel_width * hi:
+                    continue
+                mid = round(0.5 * (lo + hi), 6)
+                todo[(name, mid)] = (name, makers[name], mid)
+        if not todo:
+            break
+        if log:
+            log(f"bisection round {len(rounds)}: {len(todo)} instances")
+        run_round(list(todo.values()), net)
+
+    out = {}
+    for name, _ in pairs:
+        for k in ks:
+            lo, hi = bracket(name, k)
+            out[f"{name}/k{k}"] = {
+                "De_nominal": [lo, hi],
+                "De_measured": [seen[(name, lo)][1] if lo is not None else None,
+                                seen[(name, hi)][1] if hi is not None else None],
+                "status_at_ends": [seen[(name, lo)][2] if lo is not None else None,
+                                   seen[(name, hi)][2] if hi is not None else None],
+            }
+    return {"onsets": out, "rounds": rounds, "train_seconds": round(t_train, 2),
+            "seconds": round(time.perf_counter() - t_all, 2),
+            "cells": {f"{n}@{De:g}": v[0] for (n, De), v in sorted(seen.items())}}

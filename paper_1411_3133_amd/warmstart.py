@@ -101,14 +101,17 @@ def warm_start_run(net: Net, cases: Sequence[K.Case], plain_inits, tol: float, m
     """Batched run from the network's prediction. Instances that have not
     reached tol after fallback_after steps are run again from their plain
     start (the fallback) with the full max_steps, in a second batch; their
-    step count and the wall time include the abandoned warm phase. Returns (fields, steps, status,
-    seconds, inference_seconds, fallback_indices), fields[i] = (rho, u)."""
+    step count and the wall time include the abandoned warm phase. Returns
+    (fields, steps, status, seconds, inference_seconds, fallback_indices,
+    warm_init, observables): fields[i] = (rho, u), observables[i] =
+    (<omega>, <v_theta>, De) of the final state."""
     t0 = time.perf_counter()
     warm_init = predict_inits(net, cases)
     t_inf = time.perf_counter() - t0
     budget = max_steps if fallback_after is None else min(fallback_after, max_steps)
     bw, sw, stw, _ = run_to_steady(cases, warm_init, tol, budget, log=log)
     fields = [bw[i].moments() for i in range(len(cases))]
+    obs = [bw[i].vortex_intensity() for i in range(len(cases))]
     bw.close()
     redo = [i for i in range(len(cases)) if stw[i] != 0] if budget < max_steps else []
     if redo:
@@ -120,8 +123,9 @@ def warm_start_run(net: Net, cases: Sequence[K.Case], plain_inits, tol: float, m
             sw[i] = budget + sf[j]
             stw[i] = stf[j]
             fields[i] = bf[j].moments()
+            obs[i] = bf[j].vortex_intensity()
         bf.close()
-    return fields, sw, stw, time.perf_counter() - t0, t_inf, redo, warm_init
+    return fields, sw, stw, time.perf_counter() - t0, t_inf, redo, warm_init, obs
 
 
 def compare_starts(net: Net, cases: Sequence[K.Case], seed: int, tol: float, max_steps: int, log=None,
@@ -148,8 +152,8 @@ def compare_starts(net: Net, cases: Sequence[K.Case], seed: int, tol: float, max
     bp, sp, stp, tp = run_to_steady(cases, plain_init, tol, max_steps, log=log)
     plain_fields = [bp[i].moments() for i in range(len(cases))]
     bp.close()
-    wf, sw, stw, tw, t_inf, redo, warm_init = warm_start_run(net, cases, plain_init, tol, max_steps,
-                                                            fallback_after, log)
+    wf, sw, stw, tw, t_inf, redo, warm_init, _ = warm_start_run(net, cases, plain_init, tol, max_steps,
+                                                               fallback_after, log)
     diffs, init_err, cells = [], [], []
     for i, c in enumerate(cases):
         up, uw = plain_fields[i][1], wf[i][1]
