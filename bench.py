@@ -129,6 +129,37 @@ def time_to_steady(n_train, n_test, tol=1e-6, cap=150000):
     }
 
 
+def uneven_batch_leg(precision, steps=1000, warmup=200):
+    """Throughput of the persistent kernel on the uneven config-4 batch: 64
+    double-curved instances of 8 curvature pairs (N_r 45..96, N_phi 64..240,
+    2.9 M nodes), one launch per step over all of them, autotuned launch,
+    HIP-event time per step on the batch stream."""
+    import torch
+    from paper_1411_3133_amd import cases as K
+    from paper_1411_3133_amd import mlbm
+
+    cases = K.config4_batch(precision=precision)
+    inits = [K.perturbed_start(c, seed=3133 + i, amp=1e-4) for i, c in enumerate(cases)]
+    b = mlbm.Batch(cases, inits, stream=torch.cuda.current_stream())
+    block, grid = b.autotune(steps=10)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = b.last_step_ms()
+    nodes = sum(c.N for c in cases)
+    b.close()
+    alg = 2 * 41 * BYTES[precision] * nodes
+    return {"workload": "config4 batch: 64 ellipsoid slabs, 8 curvature pairs (R2/R1 0.25..4, N_r 45..96, "
+                        "N_phi 64..240), De 20..200, 1e-4 perturbation",
+            "nodes": nodes, "storage": precision, "launch": {"block": block, "grid": grid},
+            "MLUPS": round(nodes * steps / wall / 1e6, 1),
+            "achieved_GBs": round(alg / (ev_ms * 1e-3) / 1e9, 1),
+            "frac": round(alg / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def critical_dean_leg(tol=1e-7):
     """Critical Dean numbers (onset of 2, 4 and 6 cells) of the stable
     curvature pairs of the batched sweep, at N_r = 32, by batched bisection to
@@ -187,6 +218,7 @@ def main():
                     help="unseen cases in the time-to-steady leg (0 skips it)")
     ap.add_argument("--steady-train", type=int, default=64, help="training fields for the warm start")
     ap.add_argument("--critical", type=int, default=1, help="run the critical-De leg (0 skips it)")
+    ap.add_argument("--uneven", type=int, default=1, help="time the uneven config-4 batch (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -277,6 +309,8 @@ def main():
         "health": {"unstable": bad, "max_residual": max(res)},
     }
     batch.close()
+    if args.uneven:
+        line["uneven_batch"] = uneven_batch_leg(args.precision)
     if args.steady > 0:
         line["time_to_steady"] = time_to_steady(args.steady_train, args.steady)
     if args.critical:

@@ -180,6 +180,42 @@ def test_sampled_one_step_at_full_size(prec, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("workload", ["config2", "config4"])
+def test_batched_step_kernel_at_full_size(workload):
+    """The autotuned batched step kernel (the launch bench.py times) on the
+    full config-2 sweep (31 instances) and the uneven config-4 batch (64
+    instances, 2.9 M nodes): after 150 steps, one more step; the stored
+    populations of sampled nodes (walls, corners, interior) of three
+    instances of different shapes match the FP64 oracle applied to the
+    pre-step state, to FP32 rounding."""
+    if workload == "config2":
+        cases = K.config2_sweep(precision="f32")
+        picks = [0, 15, 30]
+    else:
+        cases = K.config4_batch(precision="f32")
+        picks = [0, 44, 55]          # pairs 0, 5, 6: different n1, n3 and tau
+    inits = [K.perturbed_start(c, seed=1411 + i, amp=1e-2) for i, c in enumerate(cases)]
+    b = mlbm.Batch(cases, inits)
+    b.autotune(steps=5)
+    b.step(150)
+    states = {i: b[i].get_f() for i in picks}
+    b.step(1)
+    _, w, _, _ = O.lattice()
+    rng = np.random.default_rng(5)
+    for i in picks:
+        c = cases[i]
+        new = b[i].get_f().reshape(41, -1)
+        n1, n2, n3 = c.n1, c.n2, c.n3
+        corners = [((x1 * n2 + x2) * n3 + x3) for x1 in (0, 1, 2, n1 - 3, n1 - 1) for x2 in (0, n2 - 1)
+                   for x3 in (0, 1, 2, n3 // 2, n3 - 3, n3 - 1)]
+        nodes = np.unique(np.concatenate([corners, rng.integers(0, c.N, 300)]))
+        ref = O.Sim(c.replace(precision="f64")).step_nodes(states[i], nodes)
+        err = (np.abs(new[:, nodes].T - ref) / w[None, :]).max()
+        print(f"{workload} instance {i} ({n1}x{n2}x{n3}): max |df|/w = {err:.3e}")
+        assert err < 1e-5
+    b.close()
+
+
 def test_window_residual_matches_oracle():
     case = K.cylinder_case(0.9, 8, 2, 8, 0.8, De=10.0, walls3=True).replace(precision="f64", check_every=20)
     init = K.perturbed_start(case, seed=4, amp=0.05, U_nom=0.05)
