@@ -166,6 +166,9 @@ void destroy_graph(Batch *B)
 }
 
 // Tile queue of the active instances for the current block size.
+// The 16-bit storage formats keep a per-row reference table.
+bool uses_ref(int st) { return st == ST_F16 || st == ST_BF16; }
+
 mlbm_status build_tiles(Batch *B)
 {
     std::vector<Tile> tiles;
@@ -319,6 +322,8 @@ void free_batch(Batch *B)
         if (I.hd.f[0]) (void)hipFree(I.hd.f[0]);
         if (I.hd.f[1]) (void)hipFree(I.hd.f[1]);
         if (I.hd.usnap) (void)hipFree(I.hd.usnap);
+        if (I.hd.ref) (void)hipFree(const_cast<float *>(I.hd.ref));
+        if (I.hd.ctr) (void)hipFree(I.hd.ctr);
     }
     for (auto &g : B->geos)
         if (g.ptr) (void)hipFree(g.ptr);
@@ -411,6 +416,19 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
             return bail(fail(MLBM_E_OOM, "population allocation failed (instance " + std::to_string(i) + ")"));
         if (hipMemsetAsync(h.usnap, 0, sizeof(double) * 3 * (size_t)h.N, B->stream) != hipSuccess)
             return bail(fail(MLBM_E_HIP, "hipMemsetAsync failed"));
+        h.ref = nullptr;
+        h.ctr = nullptr;
+        h.salt = mix32(0x3133u + (uint32_t)i);
+        if (uses_ref(B->st)) {
+            float *ref = nullptr;
+            if (hipMalloc(&ref, sizeof(float) * 2 * Q * (size_t)h.n1) != hipSuccess)
+                return bail(fail(MLBM_E_OOM, "reference table allocation failed"));
+            h.ref = ref;
+            if (hipMalloc(&h.ctr, 2 * sizeof(uint32_t)) != hipSuccess)
+                return bail(fail(MLBM_E_OOM, "step counter allocation failed"));
+            if (hipMemsetAsync(h.ctr, 0, 2 * sizeof(uint32_t), B->stream) != hipSuccess)
+                return bail(fail(MLBM_E_HIP, "hipMemsetAsync failed"));
+        }
     }
     mlbm_status s = build_tiles(B);
     if (s != MLBM_OK) return bail(s);
@@ -425,7 +443,9 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
                 return bail(fail(MLBM_E_HIP, "init_u upload failed"));
             }
         }
-        hipError_t e = launch_init(B->d_insts + i, I.hd, B->st, du, 0, B->stream);
+        hipError_t e = hipSuccess;
+        if (I.hd.ref) e = launch_ref(B->d_insts + i, I.hd, du, const_cast<float *>(I.hd.ref), B->stream);
+        if (e == hipSuccess) e = launch_init(B->d_insts + i, I.hd, B->st, du, 0, B->stream);
         (void)hipStreamSynchronize(B->stream);
         if (du) (void)hipFree(du);
         if (e != hipSuccess) return bail(fail(MLBM_E_HIP, std::string("init kernel: ") + hipGetErrorString(e)));
@@ -788,6 +808,7 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
     if (steps & 1) ++steps;
     // back up the current populations of the active instances
     std::vector<void *> backup(B->inst.size(), nullptr);
+    std::vector<uint32_t> ctr_backup(2 * B->inst.size(), 0);   // stochastic-rounding step counters
     const size_t sb = storage_bytes(B->st);
     for (size_t i = 0; i < B->inst.size(); ++i) {
         Instance &I = B->inst[i];
@@ -795,6 +816,9 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
         const size_t bytes = sb * Q * (size_t)I.hd.N;
         HIP_TRY(hipMalloc(&backup[i], bytes));
         HIP_TRY(hipMemcpyAsync(backup[i], I.hd.f[parity_of(I)], bytes, hipMemcpyDeviceToDevice, B->stream));
+        if (I.hd.ctr)
+            HIP_TRY(hipMemcpyAsync(ctr_backup.data() + 2 * i, I.hd.ctr, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                   B->stream));
     }
     const int blocks[4] = {64, 128, 256, 512};
     const int grids[4] = {0, 2 * B->num_cu, 4 * B->num_cu, 8 * B->num_cu};
@@ -848,6 +872,9 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
         const size_t bytes = sb * Q * (size_t)I.hd.N;
         if (hipMemcpyAsync(I.hd.f[parity_of(I)], backup[i], bytes, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
             st = MLBM_E_HIP;
+        if (I.hd.ctr && hipMemcpyAsync(I.hd.ctr, ctr_backup.data() + 2 * i, 2 * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                       B->stream) != hipSuccess)
+            st = MLBM_E_HIP;
     }
     if (hipStreamSynchronize(B->stream) != hipSuccess) st = MLBM_E_HIP;
     for (void *p : backup)
@@ -867,7 +894,7 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
 
 // ---------------- checkpoints ---------------------------------------------
 
-static const char CK_MAGIC[8] = {'M', 'L', 'B', 'M', 'C', 'K', '0', '2'};
+static const char CK_MAGIC[8] = {'M', 'L', 'B', 'M', 'C', 'K', '0', '4'};
 
 mlbm_status mlbm_save(mlbm_handle h, const char *path)
 {
@@ -877,11 +904,17 @@ mlbm_status mlbm_save(mlbm_handle h, const char *path)
     const size_t N = (size_t)I->hd.N, sb = storage_bytes(B->st);
     std::vector<char> pops(sb * Q * N);
     std::vector<double> us(3 * N);
+    std::vector<float> ref(I->hd.ref ? (size_t)2 * Q * I->hd.n1 : 0);
     std::vector<WindowState> ws;
     mlbm_status s = read_ws(B, ws);
     if (s != MLBM_OK) return s;
     HIP_TRY(hipMemcpyAsync(pops.data(), I->hd.f[parity_of(*I)], pops.size(), hipMemcpyDeviceToHost, B->stream));
     HIP_TRY(hipMemcpyAsync(us.data(), I->hd.usnap, sizeof(double) * us.size(), hipMemcpyDeviceToHost, B->stream));
+    uint32_t ctr = 0;
+    if (!ref.empty()) {
+        HIP_TRY(hipMemcpyAsync(ref.data(), I->hd.ref, sizeof(float) * ref.size(), hipMemcpyDeviceToHost, B->stream));
+        HIP_TRY(hipMemcpyAsync(&ctr, I->hd.ctr + parity_of(*I), sizeof(uint32_t), hipMemcpyDeviceToHost, B->stream));
+    }
     HIP_TRY(hipStreamSynchronize(B->stream));
     FILE *fp = fopen(path, "wb");
     if (!fp) return fail(MLBM_E_IO, std::string("cannot open ") + path);
@@ -890,7 +923,9 @@ mlbm_status mlbm_save(mlbm_handle h, const char *path)
     const int64_t t = I->t;
     bool ok = fwrite(CK_MAGIC, 1, 8, fp) == 8 && fwrite(&d, sizeof(d), 1, fp) == 1 && fwrite(&t, sizeof(t), 1, fp) == 1 &&
               fwrite(&ws[h->idx], sizeof(WindowState), 1, fp) == 1 && fwrite(pops.data(), 1, pops.size(), fp) == pops.size() &&
-              fwrite(us.data(), sizeof(double), us.size(), fp) == us.size();
+              fwrite(us.data(), sizeof(double), us.size(), fp) == us.size() &&
+              fwrite(ref.data(), sizeof(float), ref.size(), fp) == ref.size() &&
+              (ref.empty() || fwrite(&ctr, sizeof(ctr), 1, fp) == 1);
     ok = (fclose(fp) == 0) && ok;
     return ok ? MLBM_OK : fail(MLBM_E_IO, std::string("write failed: ") + path);
 }
@@ -918,7 +953,11 @@ mlbm_status mlbm_load(const char *path, void *hip_stream, mlbm_handle *out)
     const size_t N = (size_t)d.n1 * d.n2 * d.n3, sb = storage_bytes(d.precision);
     std::vector<char> pops(sb * Q * N);
     std::vector<double> us(3 * N);
-    ok = fread(pops.data(), 1, pops.size(), fp) == pops.size() && fread(us.data(), sizeof(double), us.size(), fp) == us.size();
+    std::vector<float> ref(uses_ref(d.precision) ? (size_t)2 * Q * d.n1 : 0);
+    uint32_t ctr = 0;
+    ok = fread(pops.data(), 1, pops.size(), fp) == pops.size() && fread(us.data(), sizeof(double), us.size(), fp) == us.size() &&
+         fread(ref.data(), sizeof(float), ref.size(), fp) == ref.size() &&
+         (ref.empty() || fread(&ctr, sizeof(ctr), 1, fp) == 1);
     fclose(fp);
     if (!ok) return fail(MLBM_E_IO, "checkpoint truncated");
     mlbm_handle h = nullptr;
@@ -931,6 +970,11 @@ mlbm_status mlbm_load(const char *path, void *hip_stream, mlbm_handle *out)
     hipError_t e = hipMemcpyAsync(I.hd.f[parity_of(I)], pops.data(), pops.size(), hipMemcpyHostToDevice, B->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(I.hd.usnap, us.data(), sizeof(double) * us.size(), hipMemcpyHostToDevice, B->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(B->d_ws, &w, sizeof(w), hipMemcpyHostToDevice, B->stream);
+    if (e == hipSuccess && !ref.empty())
+        e = hipMemcpyAsync(const_cast<float *>(I.hd.ref), ref.data(), sizeof(float) * ref.size(), hipMemcpyHostToDevice,
+                           B->stream);
+    if (e == hipSuccess && !ref.empty())
+        e = hipMemcpyAsync(I.hd.ctr + parity_of(I), &ctr, sizeof(uint32_t), hipMemcpyHostToDevice, B->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(B->stream);
     if (e != hipSuccess) {
         mlbm_destroy(h);

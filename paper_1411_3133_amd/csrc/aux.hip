@@ -83,14 +83,11 @@ hipError_t launch_geometry(double *geo, const GeoParams &p, hipStream_t s)
 // Initial state f* = f_eq(rho', U) with rho' = 1/sqrt(g) (rho = 1), in FP64
 // ------------------------------------------------------------------------
 
-template <int ST>
-__global__ void init_kernel(const InstDesc *dd, const double *init_u, int parity)
+// FP64 offsets g = f_eq - w of node n (x1 row, column col) for the initial
+// state: rho' = 1/sqrt(g), contravariant velocity init_u / s (or rest).
+__device__ void init_offsets(const InstDesc &d, int n, const double *init_u, double (&g)[Q])
 {
-    const InstDesc &d = *dd;
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= d.N) return;
-    const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
-    (void)x2;
+    const int x1 = n / d.P, col = n - x1 * d.P, x3 = col % d.n3;
     const int NX = d.n1 * d.n3g;
     const int gi = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
     const double *geo = d.geo;
@@ -108,8 +105,6 @@ __global__ void init_kernel(const InstDesc *dd, const double *init_u, int parity
     const double trD = D[0][0] + D[1][1] + D[2][2];
     double DU[3];
     for (int i = 0; i < 3; ++i) DU[i] = D[i][0] * U[0] + D[i][1] * U[1] + D[i][2] * U[2];
-    using T = typename Codec<ST>::T;
-    T *dst = (T *)d.f[parity];
     for (int q = 0; q < Q; ++q) {
         const double c0 = CV[q][0], c1 = CV[q][1], c2 = CV[q][2];
         const double cu = c0 * U[0] + c1 * U[1] + c2 * U[2];
@@ -121,10 +116,65 @@ __global__ void init_kernel(const InstDesc *dd, const double *init_u, int parity
         const double Em1 = (cDc - cs2 * trD) / (2.0 * cs2) + (cu * cu - cs2 * uu) / (2.0 * cs2 * cs2);
         const double Od = cu / cs2 + (cu * cu * cu - 3.0 * cs2 * uu * cu) / (6.0 * cs2 * cs2 * cs2)
                         + (cDc * cu - cs2 * trD * cu - 2.0 * cs2 * cDu) / (2.0 * cs2 * cs2);
-        const double w = wq(q);
-        const double g = w * ((rho - 1.0) + rho * (Em1 + Od));
-        dst[pop_elem(q, x1, col, d.P)] = Codec<ST>::from_f64(g, w);
+        g[q] = wq(q) * ((rho - 1.0) + rho * (Em1 + Od));
     }
+}
+
+// Reference offsets of the 16-bit storage formats: per x1 row and
+// population, the row mean r of d = f/w - 1 of the initial state (table
+// [n1][41], followed by w r [n1][41] for decoding). Values
+// are stored as d - ref, which keeps the stored magnitudes (and so the
+// rounding error) small wherever the flow stays near its row mean. One
+// workgroup per row, fixed summation order.
+__global__ void ref_kernel(const InstDesc *dd, const double *init_u, float *ref)
+{
+    const InstDesc &d = *dd;
+    const int x1 = blockIdx.x;
+    __shared__ double part[256];
+    double acc[Q];
+    for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+    for (int col = threadIdx.x; col < d.P; col += blockDim.x) {
+        double g[Q];
+        init_offsets(d, x1 * d.P + col, init_u, g);
+        for (int q = 0; q < Q; ++q) acc[q] += g[q] / wq(q);
+    }
+    for (int q = 0; q < Q; ++q) {
+        part[threadIdx.x] = acc[q];
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const float r = (float)(part[0] / d.P);
+            ref[x1 * Q + q] = r;
+            ref[(d.n1 + x1) * Q + q] = (float)wq(q) * r;   // w r, for decoding
+        }
+        __syncthreads();
+    }
+}
+
+template <int ST>
+__global__ void init_kernel(const InstDesc *dd, const double *init_u, int parity)
+{
+    const InstDesc &d = *dd;
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= d.N) return;
+    const int x1 = n / d.P, col = n - x1 * d.P;
+    double g[Q];
+    init_offsets(d, n, init_u, g);
+    using T = typename Codec<ST>::T;
+    T *dst = (T *)d.f[parity];
+    for (int q = 0; q < Q; ++q) {
+        const double r = Codec<ST>::REF ? (double)d.ref[x1 * Q + q] : 0.0;
+        dst[pop_elem(q, x1, col, d.P)] = Codec<ST>::from_f64(g[q], wq(q), r);
+    }
+}
+
+hipError_t launch_ref(const InstDesc *d_desc, const InstDesc &h, const double *init_u, float *ref, hipStream_t s)
+{
+    hipLaunchKernelGGL(ref_kernel, dim3(h.n1), dim3(256), 0, s, d_desc, init_u, ref);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(const InstDesc *d_desc, const InstDesc &h, int st, const double *init_u, int parity,
@@ -183,7 +233,8 @@ __device__ __forceinline__ void pull_f64(const InstDesc &d, int parity, int x1, 
         int row;
         const int col = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip, row);
         const int qs = flip ? qo : (int)q;
-        g[q] = Codec<ST>::to_f64(gload<T>(src, sizeof(T) * pop_elem(qs, row, col, d.P)), wq(q));
+        const double r = Codec<ST>::REF ? (double)d.ref[row * Q + qs] : 0.0;
+        g[q] = Codec<ST>::to_f64(gload<T>(src, sizeof(T) * pop_elem(qs, row, col, d.P)), wq(q), r);
     });
 }
 
@@ -302,7 +353,8 @@ __global__ void decode_kernel(InstDesc d, int parity, double *f)
     const int q = (int)(i / d.N);
     const int n = (int)(i - (size_t)q * d.N), x1 = n / d.P;
     const double w = wq(q);
-    f[i] = Codec<ST>::to_f64(((const T *)d.f[parity])[pop_elem(q, x1, n - x1 * d.P, d.P)], w) + w;
+    const double r = Codec<ST>::REF ? (double)d.ref[x1 * Q + q] : 0.0;
+    f[i] = Codec<ST>::to_f64(((const T *)d.f[parity])[pop_elem(q, x1, n - x1 * d.P, d.P)], w, r) + w;
 }
 
 template <int ST>
@@ -314,7 +366,8 @@ __global__ void encode_kernel(InstDesc d, int parity, const double *f)
     const int q = (int)(i / d.N);
     const int n = (int)(i - (size_t)q * d.N), x1 = n / d.P;
     const double w = wq(q);
-    ((T *)d.f[parity])[pop_elem(q, x1, n - x1 * d.P, d.P)] = Codec<ST>::from_f64(f[i] - w, w);
+    const double r = Codec<ST>::REF ? (double)d.ref[x1 * Q + q] : 0.0;
+    ((T *)d.f[parity])[pop_elem(q, x1, n - x1 * d.P, d.P)] = Codec<ST>::from_f64(f[i] - w, w, r);
 }
 
 hipError_t launch_decode(const InstDesc &h, int st, int parity, double *f, hipStream_t s)
@@ -362,15 +415,23 @@ __global__ void step_nodes_kernel(const InstDesc *dd, int parity, const int64_t 
     if (n < 0 || n >= d.N) return;
     const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
     typename Codec<ST>::G g[Q];
-    gather_general<ST>(d.f[parity], d, x1, x2, x3, g);
+    gather_general<ST>(d.f[parity], d, x1, x2, x3, RefRow{d.ref, d.n1}, g);
     NodeGeo<PAT, C> geo;
     geo.load(d.geo, x1 * d.n3g + (d.n3g > 1 ? x3 : 0), d.n1 * d.n3g, (C)d.force);
     C rho, u[3];
     collide<PAT, C, typename Codec<ST>::G>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
     static_for<0, Q>([&](auto q) {
         // round through the storage format, as the step kernel stores it
-        const T tmp = Codec<ST>::encode(g[q], (C)(1.0 / wq(q)));
-        out[k * Q + q] = Codec<ST>::to_f64(tmp, wq(q)) + wq(q);
+        const float r = Codec<ST>::REF ? d.ref[x1 * Q + q] : 0.0f;
+        // the rounding the step kernel applies in the step that reads the
+        // current counter (stochastic for the 16-bit formats)
+        T tmp;
+        if constexpr (Codec<ST>::REF)
+            tmp = Codec<ST>::encode_sr(g[q], (C)(1.0 / wq(q)), (C)r,
+                                       RoundBits(d.salt, (uint32_t)n, d.ctr[parity]).template get<q>());
+        else
+            tmp = Codec<ST>::encode(g[q], (C)(1.0 / wq(q)), (C)r);
+        out[k * Q + q] = Codec<ST>::to_f64(tmp, wq(q), (double)r) + wq(q);
     });
 }
 

@@ -42,6 +42,9 @@ struct InstDesc {
     void *f[2];            // population buffers
     const double *geo;     // [NGEO][n1*n3g]
     double *usnap;         // [3][N]
+    const float *ref;      // FP16/BF16 storage: per-row reference r [n1][41], then w r [n1][41]; else null
+    uint32_t *ctr;         // FP16/BF16 storage: step counter [2] (read [parity], next in [parity ^ 1])
+    uint32_t salt;         // per-instance key of the stochastic rounding
     int n1, n2, n3, walls;
     int P, N;              // n2*n3, n1*n2*n3
     int n3g;               // 1 or n3
@@ -96,70 +99,135 @@ __device__ __forceinline__ float bf16_bits_to_float(uint16_t h)
     return __uint_as_float(((uint32_t)h) << 16);
 }
 
-// round to nearest even; NaN stays NaN
+// round to nearest even; NaN stays NaN (a select, not a branch)
 __device__ __forceinline__ uint16_t float_to_bf16_bits(float x)
 {
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const uint32_t u = __float_as_uint(x);
+    const uint32_t rounded = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t quiet = (u >> 16) | 0x40u;
+    return (uint16_t)(((u & 0x7fffffffu) > 0x7f800000u) ? quiet : rounded);
 }
 
 __device__ __forceinline__ float f16_bits_to_float(uint16_t h) { return __half2float(__ushort_as_half(h)); }
 __device__ __forceinline__ uint16_t float_to_f16_bits(float x) { return __half_as_ushort(__float2half_rn(x)); }
 
+// Stochastic rounding with the CDNA4 conversions v_cvt_sr_f16_f32 and
+// v_cvt_sr_bf16_f32: the magnitude of x is rounded up with probability
+// equal to the dropped fraction, taken from the top bits of `seed` (13 of
+// them for binary16, 16 for bfloat16; a seed whose random bits sit in the
+// low half always truncates -- measured on the part). Each rounding is
+// unbiased, so increments below the storage resolution (the per-step body
+// force, for one) are kept on average instead of being lost.
+typedef _Float16 mlbm_h2 __attribute__((ext_vector_type(2)));
+typedef __bf16 mlbm_b2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint16_t float_to_f16_bits_sr(float x, uint32_t seed)
+{
+    const mlbm_h2 v = __builtin_amdgcn_cvt_sr_f16_f32(mlbm_h2{}, x, seed, false);
+    const _Float16 lo = v.x;
+    return __builtin_bit_cast(uint16_t, lo);
+}
+__device__ __forceinline__ uint16_t float_to_bf16_bits_sr(float x, uint32_t seed)
+{
+    const mlbm_b2 v = __builtin_amdgcn_cvt_sr_bf16_f32(mlbm_b2{}, x, seed, false);
+    const __bf16 lo = v.x;
+    return __builtin_bit_cast(uint16_t, lo);
+}
+
+// 32-bit integer hash (xorshift-multiply, two rounds).
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
 // T: stored type; C: compute type.  decode/encode map stored values to and
-// from the offset g = f - w (w = weight of the population).
+// from the offset g = f - w (w = weight of the population). The 16-bit
+// formats store d = f/w - 1 - r, where r is the reference offset of the
+// population in the row the value is stored in (REF): decode takes
+// wr = w r and returns g = w d + wr, encode takes r. The wide formats ignore
+// the reference.
 template <int ST> struct Codec;
 
 template <> struct Codec<ST_F64> {
     using T = double;
     using C = double;
     using G = double;     // register type of the 41 populations
-    __device__ static __forceinline__ C decode(T v, C) { return v; }
-    __device__ static __forceinline__ T encode(C g, C) { return g; }
-    __device__ static __forceinline__ double to_f64(T v, double) { return v; }
-    __device__ static __forceinline__ T from_f64(double g, double) { return g; }
+    static constexpr bool REF = false;
+    __device__ static __forceinline__ C decode(T v, C, C) { return v; }
+    __device__ static __forceinline__ T encode(C g, C, C) { return g; }
+    __device__ static __forceinline__ T encode_sr(C g, C, C, uint32_t) { return g; }
+    __device__ static __forceinline__ double to_f64(T v, double, double) { return v; }
+    __device__ static __forceinline__ T from_f64(double g, double, double) { return g; }
 };
 
 template <> struct Codec<ST_F32> {
     using T = float;
     using C = float;
     using G = float;
-    __device__ static __forceinline__ C decode(T v, C) { return v; }
-    __device__ static __forceinline__ T encode(C g, C) { return g; }
-    __device__ static __forceinline__ double to_f64(T v, double) { return (double)v; }
-    __device__ static __forceinline__ T from_f64(double g, double) { return (float)g; }
+    static constexpr bool REF = false;
+    __device__ static __forceinline__ C decode(T v, C, C) { return v; }
+    __device__ static __forceinline__ T encode(C g, C, C) { return g; }
+    __device__ static __forceinline__ T encode_sr(C g, C, C, uint32_t) { return g; }
+    __device__ static __forceinline__ double to_f64(T v, double, double) { return (double)v; }
+    __device__ static __forceinline__ T from_f64(double g, double, double) { return (float)g; }
 };
 
 template <> struct Codec<ST_F32D> {   // FP32 storage, FP64 collision, FP32 registers
     using T = float;
     using C = double;
     using G = float;
-    __device__ static __forceinline__ G decode(T v, C) { return v; }
-    __device__ static __forceinline__ T encode(G g, C) { return g; }
-    __device__ static __forceinline__ double to_f64(T v, double) { return (double)v; }
-    __device__ static __forceinline__ T from_f64(double g, double) { return (float)g; }
+    static constexpr bool REF = false;
+    __device__ static __forceinline__ G decode(T v, C, C) { return v; }
+    __device__ static __forceinline__ T encode(G g, C, C) { return g; }
+    __device__ static __forceinline__ T encode_sr(G g, C, C, uint32_t) { return g; }
+    __device__ static __forceinline__ double to_f64(T v, double, double) { return (double)v; }
+    __device__ static __forceinline__ T from_f64(double g, double, double) { return (float)g; }
 };
 
 template <> struct Codec<ST_F16> {
-    using T = uint16_t;    // IEEE binary16 bits of d = f / w - 1
+    using T = uint16_t;    // IEEE binary16 bits of d = f / w - 1 - r
     using C = float;
     using G = float;
-    __device__ static __forceinline__ C decode(T v, C w) { return w * f16_bits_to_float(v); }
-    __device__ static __forceinline__ T encode(C g, C inv_w) { return float_to_f16_bits(g * inv_w); }
-    __device__ static __forceinline__ double to_f64(T v, double w) { return w * (double)f16_bits_to_float(v); }
-    __device__ static __forceinline__ T from_f64(double g, double w) { return float_to_f16_bits((float)(g / w)); }
+    static constexpr bool REF = true;
+    __device__ static __forceinline__ C decode(T v, C w, C wr) { return fmaf(f16_bits_to_float(v), w, wr); }
+    __device__ static __forceinline__ T encode(C g, C inv_w, C r) { return float_to_f16_bits(fmaf(g, inv_w, -r)); }
+    __device__ static __forceinline__ T encode_sr(C g, C inv_w, C r, uint32_t rnd)
+    {
+        return float_to_f16_bits_sr(fmaf(g, inv_w, -r), rnd);
+    }
+    __device__ static __forceinline__ double to_f64(T v, double w, double r)
+    {
+        return w * ((double)f16_bits_to_float(v) + r);
+    }
+    __device__ static __forceinline__ T from_f64(double g, double w, double r)
+    {
+        return float_to_f16_bits((float)(g / w - r));
+    }
 };
 
 template <> struct Codec<ST_BF16> {
-    using T = uint16_t;    // bfloat16 bits of d = f / w - 1
+    using T = uint16_t;    // bfloat16 bits of d = f / w - 1 - r
     using C = float;
     using G = float;
-    __device__ static __forceinline__ C decode(T v, C w) { return w * bf16_bits_to_float(v); }
-    __device__ static __forceinline__ T encode(C g, C inv_w) { return float_to_bf16_bits(g * inv_w); }
-    __device__ static __forceinline__ double to_f64(T v, double w) { return w * (double)bf16_bits_to_float(v); }
-    __device__ static __forceinline__ T from_f64(double g, double w) { return float_to_bf16_bits((float)(g / w)); }
+    static constexpr bool REF = true;
+    __device__ static __forceinline__ C decode(T v, C w, C wr) { return fmaf(bf16_bits_to_float(v), w, wr); }
+    __device__ static __forceinline__ T encode(C g, C inv_w, C r) { return float_to_bf16_bits(fmaf(g, inv_w, -r)); }
+    __device__ static __forceinline__ T encode_sr(C g, C inv_w, C r, uint32_t rnd)
+    {
+        return float_to_bf16_bits_sr(fmaf(g, inv_w, -r), rnd);
+    }
+    __device__ static __forceinline__ double to_f64(T v, double w, double r)
+    {
+        return w * ((double)bf16_bits_to_float(v) + r);
+    }
+    __device__ static __forceinline__ T from_f64(double g, double w, double r)
+    {
+        return float_to_bf16_bits((float)(g / w - r));
+    }
 };
 
 inline size_t storage_bytes(int st) { return st == ST_F64 ? 8 : (st == ST_F32 || st == ST_F32D) ? 4 : 2; }

@@ -367,6 +367,56 @@ __host__ __device__ __forceinline__ uint64_t pop_elem(int q, int x1, int col, in
     return ((uint64_t)x1 * Q + (uint64_t)q) * (uint64_t)P + (uint64_t)col;
 }
 
+// Random seeds of the stochastic rounding of node n's 41 populations in the
+// step that reads step counter c: two hashed words of (instance salt, n,
+// c); population q takes one of them rotated by its own amount (one
+// funnel shift), so the top bits the conversion consumes differ between
+// populations. Every bit of a good hash is uniform, so each rounding stays
+// unbiased; seeds of different populations overlap, which only correlates
+// their rounding. Results stay bitwise reproducible.
+struct RoundBits {
+    uint32_t a, b;
+    __device__ __forceinline__ RoundBits(uint32_t salt, uint32_t n, uint32_t c)
+    {
+        const uint32_t key = salt + n * 0x9E3779B9u + c * 0x85EBCA77u;
+        a = mix32(key);
+        b = mix32(key ^ 0x68E31DA4u);
+    }
+    template <int q> __device__ __forceinline__ uint32_t get() const
+    {
+        constexpr uint32_t rot = (uint32_t)((q * 7) & 31);
+        const uint32_t w = (q & 1) ? b : a;
+        return rot == 0 ? w : ((w << rot) | (w >> (32u - rot)));
+    }
+};
+
+// Reference offsets of the 16-bit storage formats as a gather sees them.
+// The instance's table holds r [n1][41] followed by w r [n1][41]; a view
+// answers, for the source row `row` = x1 - t of a pull and a population q,
+// r (for encoding) and w r (for decoding).
+// RefScalar: for rows uniform across the wavefront (the step kernel's
+// gathers and store), read through the scalar cache; reads only.
+// RefRow: per-lane rows (auxiliary kernels).
+#define MLBM_CONST __attribute__((address_space(4)))
+struct RefScalar {
+    const float *ref;
+    int n1;
+    __device__ __forceinline__ float get_r(int, int row, int q) const
+    {
+        return ((const MLBM_CONST float *)ref)[__builtin_amdgcn_readfirstlane(row) * Q + q];
+    }
+    __device__ __forceinline__ float get_wr(int, int row, int q) const
+    {
+        return ((const MLBM_CONST float *)ref)[(n1 + __builtin_amdgcn_readfirstlane(row)) * Q + q];
+    }
+};
+struct RefRow {
+    const float *ref;
+    int n1;
+    __device__ __forceinline__ float get_r(int, int row, int q) const { return ref[row * Q + q]; }
+    __device__ __forceinline__ float get_wr(int, int row, int q) const { return ref[(n1 + row) * Q + q]; }
+};
+
 struct LaneOffsets {
     uint32_t o2[5], o3[5];
     __device__ __forceinline__ void init(int x2, int x3, int n2, int n3, bool per3, uint32_t S)
@@ -381,26 +431,29 @@ struct LaneOffsets {
 
 // Pull from x - c inside the domain (no wall within reach): the row x1 - c1
 // is uniform across the wavefront, only the in-row byte offset is per lane.
-template <int ST>
+template <int ST, class R>
 __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, int x1, const LaneOffsets &L,
-                                            typename Codec<ST>::G (&g)[Q])
+                                            const R &ref, typename Codec<ST>::G (&g)[Q])
 {
     using T = typename Codec<ST>::T;
     using C = typename Codec<ST>::C;
     constexpr uint64_t S = sizeof(T);
     const bool per1 = !(d.walls & 1);
     const uint64_t PS = (uint64_t)d.P * S;
-    uint64_t rb[5];   // byte offset of plane 0 of the source row x1 - CVALS[s]
+    int rows[5];      // source row x1 - CVALS[s]
+    uint64_t rb[5];   // byte offset of plane 0 of that row
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         int r1 = x1 - CVALS[k];
         if (per1) r1 = wrap_axis(r1, d.n1);
+        rows[k] = r1;
         rb[k] = (uint64_t)r1 * (uint64_t)Q * PS;
     }
     static_for<0, Q>([&](auto q) {
         constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
         const void *rowp = (const char *)src + rb[cslot(c1)] + (uint64_t)q * PS;
-        g[q] = Codec<ST>::decode(gload<T>(rowp, L.o2[cslot(c2)] + L.o3[cslot(c3)]), (C)wq(q));
+        const C wr = Codec<ST>::REF ? (C)ref.get_wr(c1, rows[cslot(c1)], q) : C(0);
+        g[q] = Codec<ST>::decode(gload<T>(rowp, L.o2[cslot(c2)] + L.o3[cslot(c3)]), (C)wq(q), wr);
     });
 }
 
@@ -414,20 +467,22 @@ __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, 
 // the plain pull. Candidates are formed from per-wave row offsets and
 // per-lane in-row offsets and chosen per lane by selects, so the path has
 // no branches; byte offsets fit in 32 bits (buffers are below 4 GiB).
-template <int ST>
+template <int ST, class R>
 __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d, int x1, int x2, int x3,
-                                              const LaneOffsets &L, typename Codec<ST>::G (&g)[Q])
+                                              const LaneOffsets &L, const R &ref, typename Codec<ST>::G (&g)[Q])
 {
     using T = typename Codec<ST>::T;
     using C = typename Codec<ST>::C;
     constexpr uint32_t S = sizeof(T);
     const bool per1 = !(d.walls & 1);
     const uint32_t PS = (uint32_t)d.P * S;
-    uint32_t rb[7];   // byte offset of plane 0 of the source row x1 - t, t = -3..3
+    int rows[7];      // source row x1 - t, t = -3..3
+    uint32_t rb[7];   // byte offset of plane 0 of that row
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
         int r1 = x1 - (k - 3);
         if (per1) r1 = wrap_axis(r1, d.n1);
+        rows[k] = r1;
         rb[k] = (uint32_t)r1 * (uint32_t)Q * PS;
     }
     const uint32_t n3S = (uint32_t)d.n3 * S;
@@ -440,7 +495,9 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
         constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
         constexpr int a1 = c1 < 0 ? -c1 : c1, a2 = c2 < 0 ? -c2 : c2, a3 = c3 < 0 ? -c3 : c3;
         constexpr int m = a1 > a2 ? (a1 > a3 ? a1 : a3) : (a2 > a3 ? a2 : a3);
+        constexpr bool REF = Codec<ST>::REF;
         uint32_t off = rb[3 + c1] + (uint32_t)q * PS + L.o2[cslot(c2)] + L.o3[cslot(c3)];
+        C r = REF ? (C)ref.get_wr(c1, rows[3 + c1], q) : C(0);
         if constexpr (c3 != 0) {
             constexpr int qo = opposite(q);
             constexpr int h1 = c1 / m, h2 = c2 / m, h3 = c3 / m;
@@ -449,14 +506,21 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
             if constexpr (m == 1) {
                 const uint32_t o0 = rb[3] + base + L.o2[2] + x3S;            // sb = 0: the node itself
                 off = dist == 0 ? o0 : off;
+                if constexpr (REF) r = dist == 0 ? (C)ref.get_wr(0, rows[3], qo) : r;
             } else {
                 const uint32_t oa = rb[3 - 2 * h1] + base + o2t[3 - 2 * h2] + (uint32_t)((int)x3S + 2 * h3 * (int)S);
                 const uint32_t ob = rb[3] + base + L.o2[2] + x3S;
                 const uint32_t oc = rb[3 + 2 * h1] + base + o2t[3 + 2 * h2] + (uint32_t)((int)x3S - 2 * h3 * (int)S);
                 off = dist == 0 ? oa : (dist == 1 ? ob : (dist == 2 ? oc : off));
+                if constexpr (REF) {
+                    const C ra = (C)ref.get_wr(-2 * h1, rows[3 - 2 * h1], qo);
+                    const C rbv = (C)ref.get_wr(0, rows[3], qo);
+                    const C rc = (C)ref.get_wr(2 * h1, rows[3 + 2 * h1], qo);
+                    r = dist == 0 ? ra : (dist == 1 ? rbv : (dist == 2 ? rc : r));
+                }
             }
         }
-        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)off), (C)wq(q));
+        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)off), (C)wq(q), r);
     });
 }
 
@@ -467,9 +531,9 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
 // sb = back - m are scalars: the source row and plane are uniform and only
 // the in-row offset of x - (c/m) sb varies per lane. One x1 crossing at
 // most (a single walled axis of >= 4 nodes), as in fold_source below.
-template <int ST>
+template <int ST, class R>
 __device__ __forceinline__ void gather_x1wall(const void *src, const InstDesc &d, int x1, int x2, int x3,
-                                              const LaneOffsets &L, typename Codec<ST>::G (&g)[Q])
+                                              const LaneOffsets &L, const R &ref, typename Codec<ST>::G (&g)[Q])
 {
     using T = typename Codec<ST>::T;
     using C = typename Codec<ST>::C;
@@ -487,6 +551,7 @@ __device__ __forceinline__ void gather_x1wall(const void *src, const InstDesc &d
         constexpr int a1 = c1 < 0 ? -c1 : c1, a2 = c2 < 0 ? -c2 : c2, a3 = c3 < 0 ? -c3 : c3;
         constexpr int m = a1 > a2 ? (a1 > a3 ? a1 : a3) : (a2 > a3 ? a2 : a3);
         uint32_t rowoff, inrow;
+        int srow = x1, splane = q;                      // uniform source row and plane
         if constexpr (c1 == 0) {
             rowoff = ((uint32_t)x1 * (uint32_t)Q + (uint32_t)q) * PS;
             inrow = L.o2[cslot(c2)] + L.o3[cslot(c3)];
@@ -495,17 +560,21 @@ __device__ __forceinline__ void gather_x1wall(const void *src, const InstDesc &d
             constexpr int h1 = c1 / m, h2 = c2 / m, h3 = c3 / m;
             const int back = c1 > 0 ? lo : hi;
             if (back >= 2 * m) {                        // no crossing: the plain pull
-                rowoff = ((uint32_t)(x1 - c1) * (uint32_t)Q + (uint32_t)q) * PS;
+                srow = x1 - c1;
+                rowoff = ((uint32_t)srow * (uint32_t)Q + (uint32_t)q) * PS;
                 inrow = L.o2[cslot(c2)] + L.o3[cslot(c3)];
             } else {                                    // reflected: plane qo at x - (c/m) sb
                 const int sb = back - m;                // -2, 0 or 2 (m = 3), 0 (m = 1)
-                rowoff = ((uint32_t)(x1 - h1 * sb) * (uint32_t)Q + (uint32_t)qo) * PS;
+                srow = x1 - h1 * sb;
+                splane = qo;
+                rowoff = ((uint32_t)srow * (uint32_t)Q + (uint32_t)qo) * PS;
                 const int k = sb == 0 ? 1 : (sb > 0 ? 2 : 0);   // index of t = sb
                 const int k2 = h2 == 0 ? 1 : (h2 > 0 ? k : 2 - k), k3 = h3 == 0 ? 1 : (h3 > 0 ? k : 2 - k);
                 inrow = (k2 == 0 ? o2s[0] : (k2 == 1 ? o2s[1] : o2s[2])) + (k3 == 0 ? o3s[0] : (k3 == 1 ? o3s[1] : o3s[2]));
             }
         }
-        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(rowoff + inrow)), (C)wq(q));
+        const C r = Codec<ST>::REF ? (C)ref.get_wr(x1 - srow, srow, splane) : C(0);
+        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(rowoff + inrow)), (C)wq(q), r);
     });
 }
 
@@ -564,9 +633,9 @@ __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, i
 }
 
 // General pull (any lane position, walls on any axis).
-template <int ST>
+template <int ST, class R>
 __device__ __forceinline__ void gather_general(const void *src, const InstDesc &d, int x1, int x2, int x3,
-                                               typename Codec<ST>::G (&g)[Q])
+                                               const R &ref, typename Codec<ST>::G (&g)[Q])
 {
     using T = typename Codec<ST>::T;
     using C = typename Codec<ST>::C;
@@ -578,7 +647,9 @@ __device__ __forceinline__ void gather_general(const void *src, const InstDesc &
         const int col = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip, row);
         const uint32_t qs = flip ? (uint32_t)qo : (uint32_t)q;
         const uint32_t e = ((uint32_t)row * (uint32_t)Q + qs) * (uint32_t)d.P + (uint32_t)col;
-        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(e * S)), (C)wq(q));
+        C wr = C(0);
+        if constexpr (Codec<ST>::REF) wr = (C)RefRow{d.ref, d.n1}.get_wr(0, row, (int)qs);   // per-lane row
+        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(e * S)), (C)wq(q), wr);
     });
 }
 

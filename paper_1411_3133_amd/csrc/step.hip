@@ -43,6 +43,15 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
         const void *src = d.f[a.parity];
         void *dst = d.f[a.parity ^ 1];
         constexpr uint32_t S = sizeof(T);
+        const RefScalar R{d.ref, d.n1};
+        uint32_t ctr = 0;                      // step counter of the stochastic rounding
+        if constexpr (Codec<ST>::REF) {
+            ctr = gload<uint32_t>(d.ctr, 4ull * (uint32_t)a.parity);
+            // the instance's first tile advances the counter for the next step
+            // (nothing reads that entry during this step)
+            if (x1 == 0 && tl.chunk == 0 && threadIdx.x == 0)
+                gstore<uint32_t>(d.ctr, 4ull * (uint32_t)(a.parity ^ 1), ctr + 1u);
+        }
 
         const bool wall1_row = (d.walls & 1) && (x1 < 3 || x1 > d.n1 - 4);
         const bool near3 = valid && (d.walls & 4) && (x3 < 3 || x3 > d.n3 - 4);
@@ -54,17 +63,17 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
             if (!wall1_row && !any3) {
                 LaneOffsets L;
                 L.init(x2, x3, d.n2, d.n3, !(d.walls & 4), S);
-                gather_fast<ST>(src, d, x1, L, g);
+                gather_fast<ST>(src, d, x1, L, R, g);
             } else if (!wall1_row && d.n3 >= 5) {
                 LaneOffsets L;
                 L.init(x2, x3, d.n2, d.n3, false, S);
-                gather_x3wall<ST>(src, d, x1, x2, x3, L, g);
+                gather_x3wall<ST>(src, d, x1, x2, x3, L, R, g);
             } else if (!any3) {
                 LaneOffsets L;
                 L.init(x2, x3, d.n2, d.n3, !(d.walls & 4), S);
-                gather_x1wall<ST>(src, d, x1, x2, x3, L, g);
+                gather_x1wall<ST>(src, d, x1, x2, x3, L, R, g);
             } else {
-                gather_general<ST>(src, d, x1, x2, x3, g);
+                gather_general<ST>(src, d, x1, x2, x3, R, g);
             }
             const int gidx = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
             NodeGeo<PAT, C> geo;
@@ -74,10 +83,19 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
             const size_t n = (size_t)x1 * d.P + col;
             void *drow = (char *)dst + pop_elem(0, x1, 0, d.P) * S;
             const uint32_t loff = (uint32_t)col * S;
-            static_for<0, Q>([&](auto q) {
-                void *plane = (char *)drow + (uint64_t)q * (uint64_t)d.P * S;
-                gstore_nt<T>(plane, loff, Codec<ST>::encode(g[q], (C)(1.0 / wq(q))));
-            });
+            if constexpr (Codec<ST>::REF) {
+                const RoundBits rb(d.salt, (uint32_t)n, ctr);
+                static_for<0, Q>([&](auto q) {
+                    void *plane = (char *)drow + (uint64_t)q * (uint64_t)d.P * S;
+                    gstore_nt<T>(plane, loff,
+                                 Codec<ST>::encode_sr(g[q], (C)(1.0 / wq(q)), (C)R.get_r(0, x1, q), rb.template get<q>()));
+                });
+            } else {
+                static_for<0, Q>([&](auto q) {
+                    void *plane = (char *)drow + (uint64_t)q * (uint64_t)d.P * S;
+                    gstore_nt<T>(plane, loff, Codec<ST>::encode(g[q], (C)(1.0 / wq(q)), C(0)));
+                });
+            }
             if constexpr (CHECK) {
                 double *us = d.usnap;
 #pragma unroll

@@ -126,11 +126,13 @@ def test_config1_fp32_velocity_error(config1_oracle, prec):
 # Reduced-precision storage on the double-curved workload shape (ellipsoid,
 # R1/d = 20, tau from the Mach rule), small enough for the oracle:
 # velocity and Dean-number error against the FP64 oracle after 2000 steps.
-# FP32 (storage and arithmetic, with the exact mass/momentum bookkeeping of
-# the update) is held to the 1e-5 target.  FP16/BF16 offset storage misses
-# the 1e-3 target on this low-viscosity case; their bounds record the
-# measured errors (1.2e-2 and 0.44 on velocity) with margin.
-RP_BOUNDS = {"f32": (1e-5, 1e-5), "f32c64": (1e-5, 1e-5), "f16": (2e-2, 1e-3), "bf16": (0.6, 1e-2)}
+# Bounds are (velocity relative L2, Dean number relative error). FP32
+# (storage and arithmetic, with the exact mass/momentum bookkeeping of the
+# update) is held to the 1e-5 target. FP16 and BF16 offsets (per-row
+# reference, stochastic rounding) measure 2.6e-4 / 3e-5 and 2.0e-3 / 4e-5:
+# the FP16 bound is the 1e-3 target, the BF16 one 2.5x its measurement
+# (BF16 misses the target on this low-viscosity case).
+RP_BOUNDS = {"f32": (1e-5, 1e-5), "f32c64": (1e-5, 1e-5), "f16": (1e-3, 2e-4), "bf16": (5e-3, 2e-4)}
 
 
 @pytest.fixture(scope="module")
@@ -157,7 +159,31 @@ def test_reduced_precision_velocity_and_dean_error(ellipsoid_oracle, prec):
     assert err < bu and de_err < bd
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f16", 2e-3), ("bf16", 1.6e-2)])
+# |df|/w is the error of the stored offset d: FP32 rounding of the FP32
+# collision for f32; for the 16-bit formats stochastic rounding errs by less
+# than one unit in the last place, which for stored magnitudes below 4 is
+# 2^-8 (binary16) and 2^-5 (bfloat16).
+@pytest.mark.parametrize("prec,bound", [("f16", 1e-3), ("bf16", 2e-3)])
+def test_reduced_precision_long_run_config2(prec, bound):
+    """Config-2 instance (De = 45, 64 x 4 x 256, end walls) for 10 000 steps:
+    16-bit storage against FP64 storage on the GPU (which matches the oracle
+    to 1e-12 elsewhere). Stochastic rounding keeps the per-step force
+    increments that round-to-nearest loses (0.9 % Dean-number bias at 60 000
+    steps without it); measured 1.7e-4 (FP16) and 6.8e-4 (BF16)."""
+    case = K.config2_sweep(De_values=[45.0])[0]
+    init = K.perturbed_start(case, seed=1, amp=1e-3)
+    sims = {p: mlbm.Sim(case.replace(precision=p), init_u=init) for p in ("f64", prec)}
+    for s in sims.values():
+        s.step(10000)
+    _, u64 = sims["f64"].moments()
+    _, u = sims[prec].moments()
+    err = _rel_l2(u, u64)
+    de_err = abs(sims[prec].vortex_intensity()[2] / sims["f64"].vortex_intensity()[2] - 1)
+    print(f"config2 {prec} 10k steps: velocity rel L2 {err:.3e}, De {de_err:.2e}")
+    assert err < bound and de_err < bound
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f16", 2.0 ** -8), ("bf16", 2.0 ** -5)])
 def test_sampled_one_step_at_full_size(prec, tol):
     """Config-2 size (64 x 4 x 256, end walls): after 150 GPU steps, one more
     step of sampled nodes (corners, walls, interior) against the oracle
