@@ -54,10 +54,17 @@ typedef enum {
 typedef enum {
     MLBM_F64 = 0,         /* populations stored and collided in FP64              */
     MLBM_F32 = 1,         /* stored and collided in FP32                          */
-    MLBM_F16 = 2,         /* stored as FP16 offsets f/w - 1, collided in FP32      */
-    MLBM_BF16 = 3,        /* stored as BF16 offsets f/w - 1, collided in FP32      */
+    MLBM_F16 = 2,         /* stored as FP16 offsets, collided in FP32 (below)      */
+    MLBM_BF16 = 3,        /* stored as BF16 offsets, collided in FP32 (below)      */
     MLBM_F32_C64 = 4      /* stored in FP32, collided in FP64                     */
 } mlbm_precision;
+/* 16-bit storage: population q at a node of x1 row i is stored as
+ * f/w_q - 1 - r[i][q], r being the row mean of f/w_q - 1 of the initial
+ * state (fixed at creation, kept in checkpoints). Stores round
+ * stochastically, seeded from (instance, node, step, q), so increments
+ * below the storage resolution are kept on average; results are still
+ * bitwise reproducible run to run. mlbm_set_populations and the initial
+ * state round to nearest. */
 
 enum { MLBM_WALL_AXIS1 = 1, MLBM_WALL_AXIS3 = 4 };
 enum { MLBM_FORCING_IMPROVED = 0, MLBM_FORCING_OLD = 1 };
@@ -153,8 +160,9 @@ mlbm_status mlbm_pull_map(const mlbm_desc *d, int64_t *src_node, int32_t *src_q)
 /* Number of completed steps. */
 int64_t mlbm_time(mlbm_handle h);
 
-/* Checkpoint: raw storage-precision populations, step counter and the
- * description; resume is bitwise identical.  Errors: E_IO. */
+/* Checkpoint: raw storage-precision populations, step counter, the
+ * description and, for 16-bit storage, the reference table and the rounding
+ * step counter; resume is bitwise identical.  Errors: E_IO. */
 mlbm_status mlbm_save(mlbm_handle h, const char *path);
 mlbm_status mlbm_load(const char *path, void *hip_stream, mlbm_handle *out);
 
