@@ -242,6 +242,33 @@ def test_batched_step_kernel_at_full_size(workload):
     b.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("f16", 2.0 ** -8), ("bf16", 2.0 ** -5)])
+def test_config3_16bit_step_kernel_at_full_size(prec, tol):
+    """Config-3 shape (ellipsoid 96 x 4 x 192, R1/d = 20, R2/d = 40) in 16-bit
+    storage: after 150 steps, one more step of the step kernel; sampled
+    stored populations (walls and interior) match the FP64 oracle applied to
+    the decoded pre-step state within one unit in the last place of the
+    16-bit format (stored magnitudes below 4)."""
+    case = [c for c in K.config3_cases(precision=prec) if abs(c.r_inner - 40.0) < 1e-9][0]
+    init = K.perturbed_start(case, seed=7, amp=1e-2)
+    g = mlbm.Sim(case, init_u=init)
+    g.step(150)
+    state = g.get_f()
+    g.step(1)
+    new = g.get_f().reshape(41, -1)
+    rng = np.random.default_rng(9)
+    n1, n2, n3 = case.n1, case.n2, case.n3
+    walls = [((x1 * n2 + x2) * n3 + x3) for x1 in (0, 1, 2, n1 - 3, n1 - 2, n1 - 1) for x2 in (0, n2 - 1)
+             for x3 in (0, n3 // 2, n3 - 1)]
+    nodes = np.unique(np.concatenate([walls, rng.integers(0, case.N, 300)]))
+    ref = O.Sim(case.replace(precision="f64")).step_nodes(state, nodes)
+    _, w, _, _ = O.lattice()
+    err = (np.abs(new[:, nodes].T - ref) / w[None, :]).max()
+    print(f"config3 R2/d=40 {prec}: max |df|/w = {err:.3e}")
+    assert err < tol
+    g.close()
+
+
 def test_window_residual_matches_oracle():
     case = K.cylinder_case(0.9, 8, 2, 8, 0.8, De=10.0, walls3=True).replace(precision="f64", check_every=20)
     init = K.perturbed_start(case, seed=4, amp=0.05, U_nom=0.05)

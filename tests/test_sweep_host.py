@@ -1,0 +1,70 @@
+"""Host logic of the critical-De bisection (no GPU): the batched runs are
+replaced by a field whose cell count switches at known Dean numbers, so the
+brackets must close on those thresholds to the requested width, with one
+batch per round and only open brackets rerun."""
+import numpy as np
+import pytest
+
+from paper_1411_3133_amd import cases as K
+from paper_1411_3133_amd import sweep
+
+THRESH = {"A": {2: 31.7, 4: 47.3, 6: 99.0}, "B": {2: 55.55, 4: 58.1, 6: 58.1}}
+
+
+def _field(case, cells):
+    """u^r along x3 at mid-gap with `cells` sign changes on the periodic axis."""
+    u = np.zeros((3, case.n1, case.n2, case.n3))
+    u[1] = 1.0
+    if cells:
+        x = (np.arange(case.n3) + 0.5) / case.n3
+        u[0, case.n1 // 2] = 0.1 * K.nominal_velocity(case, case.target_De) * np.sin(np.pi * cells * x + 0.2)[None, :]
+    return u
+
+
+@pytest.fixture
+def fake_runs(monkeypatch):
+    calls = []
+
+    def fake_run(cases, inits, tol, max_steps, net=None, fallback_after=None, log=None):
+        calls.append(len(cases))
+        fields, De = [], []
+        for c in cases:
+            th = THRESH[c.label]
+            cells = max([0] + [k for k, t in th.items() if c.target_De >= t])
+            fields.append((None, _field(c, cells)))
+            De.append(0.97 * c.target_De)
+        n = len(cases)
+        return fields, np.full(n, 1000), np.zeros(n, np.int32), np.array(De), 0.01
+
+    monkeypatch.setattr(sweep, "_run", fake_run)
+    return calls
+
+
+def test_brackets_close_on_thresholds(fake_runs):
+    pairs = [(name, (lambda De, name=name: K.ellipsoid_case(20.0, 30.0, 8, 2, 40, 0.6, De=De, label=name)))
+             for name in ("A", "B")]
+    grid = [20.0 + 10.0 * i for i in range(8)]
+    r = sweep.critical_dean(pairs, grid, ks=(2, 4, 6), rel_width=0.01)
+    for name in ("A", "B"):
+        for k in (2, 4, 6):
+            lo, hi = r["onsets"][f"{name}/k{k}"]["De_nominal"]
+            t = THRESH[name][k]
+            if t > grid[-1]:
+                assert hi is None and lo == grid[-1]
+                continue
+            assert lo < t <= hi and hi - lo <= 0.01 * hi
+            m_lo, m_hi = r["onsets"][f"{name}/k{k}"]["De_measured"]
+            assert m_lo == pytest.approx(0.97 * lo) and m_hi == pytest.approx(0.97 * hi)
+    # round 0 is the whole grid in one batch; later rounds only the open
+    # brackets (at most one midpoint per pair and k, shared midpoints once)
+    assert fake_runs[0] == 2 * len(grid)
+    assert all(n <= 2 * 3 for n in fake_runs[1:])
+    assert len(r["rounds"]) == len(fake_runs)
+
+
+def test_onset_below_grid_is_open(fake_runs):
+    pairs = [("A", lambda De: K.ellipsoid_case(20.0, 30.0, 8, 2, 40, 0.6, De=De, label="A"))]
+    r = sweep.critical_dean(pairs, [40.0, 50.0, 60.0], ks=(2,), rel_width=0.01)
+    lo, hi = r["onsets"]["A/k2"]["De_nominal"]
+    assert lo is None and hi == 40.0       # already 2 cells at the lowest De: no bracket
+    assert len(fake_runs) == 1
