@@ -56,6 +56,7 @@ struct Instance {
 
 struct GeoEntry {
     double *ptr = nullptr;
+    float *fptr = nullptr;     // the same values rounded to FP32
     int kind, n1, n3;
     double r_inner, width, b;
 };
@@ -302,8 +303,12 @@ GeoEntry *find_or_make_geo(Batch *B, const mlbm_desc &d, int &key, mlbm_status &
     p.r_inner = d.r_inner; p.width = d.width; p.b = d.b;
     scales(d, p.dt, p.s);
     e = launch_geometry(g.ptr, p, B->stream);
+    const long count = (long)NGEO * d.n1 * n3g;
+    if (e == hipSuccess) e = hipMalloc(&g.fptr, sizeof(float) * count);
+    if (e == hipSuccess) e = launch_geo_to_f32(g.ptr, g.fptr, count, B->stream);
     if (e != hipSuccess) {
         (void)hipFree(g.ptr);
+        if (g.fptr) (void)hipFree(g.fptr);
         st = fail(MLBM_E_HIP, std::string("geometry kernel: ") + hipGetErrorString(e));
         return nullptr;
     }
@@ -325,8 +330,10 @@ void free_batch(Batch *B)
         if (I.hd.ref) (void)hipFree(const_cast<float *>(I.hd.ref));
         if (I.hd.ctr) (void)hipFree(I.hd.ctr);
     }
-    for (auto &g : B->geos)
+    for (auto &g : B->geos) {
         if (g.ptr) (void)hipFree(g.ptr);
+        if (g.fptr) (void)hipFree(g.fptr);
+    }
     if (B->d_insts) (void)hipFree(B->d_insts);
     if (B->d_tiles) (void)hipFree(B->d_tiles);
     if (B->d_ntiles) (void)hipFree(B->d_ntiles);
@@ -401,6 +408,7 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
         if (!g) return bail(gs);
         InstDesc &h = I.hd;
         h.geo = g->ptr;
+        h.geof = g->fptr;
         h.n1 = d.n1; h.n2 = d.n2; h.n3 = d.n3; h.walls = d.walls;
         h.P = d.n2 * d.n3;
         h.N = d.n1 * h.P;

@@ -72,6 +72,19 @@ __global__ void geometry_kernel(double *geo, GeoParams p)
     put(G_X3, X3);
 }
 
+__global__ void geo_to_f32_kernel(const double *geo, float *geof, long count)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) geof[i] = (float)geo[i];
+}
+
+hipError_t launch_geo_to_f32(const double *geo, float *geof, long count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(geo_to_f32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, geo, geof, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_geometry(double *geo, const GeoParams &p, hipStream_t s)
 {
     const int NX = p.n1 * p.n3g;
@@ -417,7 +430,7 @@ __global__ void step_nodes_kernel(const InstDesc *dd, int parity, const int64_t 
     typename Codec<ST>::G g[Q];
     gather_general<ST>(d.f[parity], d, x1, x2, x3, RefRow{d.ref, d.n1}, g);
     NodeGeo<PAT, C> geo;
-    geo.load(d.geo, x1 * d.n3g + (d.n3g > 1 ? x3 : 0), d.n1 * d.n3g, (C)d.force);
+    geo.load(d.geo, d.geof, x1 * d.n3g + (d.n3g > 1 ? x3 : 0), d.n1 * d.n3g, (C)d.force);
     C rho, u[3];
     collide<PAT, C, typename Codec<ST>::G>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
     static_for<0, Q>([&](auto q) {

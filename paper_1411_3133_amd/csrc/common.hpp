@@ -41,6 +41,7 @@ enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3, ST_F32D = 4 };
 struct InstDesc {
     void *f[2];            // population buffers
     const double *geo;     // [NGEO][n1*n3g]
+    const float *geof;     // the same geometry rounded to FP32 (read by FP32 arithmetic)
     double *usnap;         // [3][N]
     const float *ref;      // FP16/BF16 storage: per-row reference r [n1][41], then w r [n1][41]; else null
     uint32_t *ctr;         // FP16/BF16 storage: step counter [2] (read [parity], next in [parity ^ 1])

@@ -76,19 +76,33 @@ struct NodeGeo {
     C Gm[3][3][3];    // Gamma^i_jk (symmetric in jk)
     C Fe[3];          // external force (lattice units)
 
-    __device__ __forceinline__ void load(const double *__restrict__ geo, int idx, int stride, C force)
+    // field f at cross-section index idx: from the FP64 precompute, or for
+    // FP32 arithmetic from its FP32 copy (the same values rounded once, so
+    // the results are identical and the geometry traffic halves)
+    __device__ __forceinline__ C field(const double *__restrict__ geo, const float *__restrict__ geof, int f, int idx,
+                                       int stride) const
+    {
+        const uint32_t e = (uint32_t)(f * stride) + (uint32_t)idx;
+        if constexpr (std::is_same<C, float>::value)
+            return gload<float>(geof, 4ull * e);
+        else
+            return (C)gload<double>(geo, 8ull * e);
+    }
+
+    __device__ __forceinline__ void load(const double *__restrict__ geo, const float *__restrict__ geof, int idx,
+                                         int stride, C force)
     {
         static_for<0, 3>([&](auto I) {
             static_for<0, 3>([&](auto J) {
                 if constexpr (Mask<PAT>::D(I, J))
-                    D[I][J] = (C)gload<double>(geo, 8ull * ((uint32_t)(d_field(I, J) * stride) + (uint32_t)idx));
+                    D[I][J] = field(geo, geof, d_field(I, J), idx, stride);
                 static_for<0, 3>([&](auto K) {
                     if constexpr (Mask<PAT>::G(I, J < K ? J : K, J < K ? K : J))
-                        Gm[I][J][K] = (C)gload<double>(geo, 8ull * ((uint32_t)(g_field(I, J, K) * stride) + (uint32_t)idx));
+                        Gm[I][J][K] = field(geo, geof, g_field(I, J, K), idx, stride);
                 });
             });
             if constexpr (Mask<PAT>::F(I))
-                Fe[I] = force * (C)gload<double>(geo, 8ull * ((uint32_t)((G_F1 + I) * stride) + (uint32_t)idx));
+                Fe[I] = force * field(geo, geof, G_F1 + I, idx, stride);
         });
     }
 };

@@ -26,6 +26,7 @@ hipError_t launch_geometry(double *geo, const GeoParams &p, hipStream_t s);
 
 // f* = f_eq(rho' = 1/sqrt(g), u) for one instance; init_u (device, physical
 // [3][N]) may be null
+hipError_t launch_geo_to_f32(const double *geo, float *geof, long count, hipStream_t s);
 hipError_t launch_ref(const InstDesc *d_desc, const InstDesc &h_desc, const double *init_u, float *ref,
                       hipStream_t s);
 hipError_t launch_init(const InstDesc *d_desc, const InstDesc &h_desc, int st, const double *init_u,

@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
             }
             const int gidx = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
             NodeGeo<PAT, C> geo;
-            geo.load(d.geo, gidx, d.n1 * d.n3g, (C)d.force);
+            geo.load(d.geo, d.geof, gidx, d.n1 * d.n3g, (C)d.force);
             C rho, u[3];
             collide<PAT, C, typename Codec<ST>::G>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
             const size_t n = (size_t)x1 * d.P + col;
