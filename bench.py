@@ -16,7 +16,6 @@ kernel runs on) and the FP64 CPU oracle timed on the host cores.
 import argparse
 import hashlib
 import json
-import math
 import os
 import re
 import sys

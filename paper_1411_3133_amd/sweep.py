@@ -12,7 +12,7 @@ fallback). Orchestration only: every step runs in libmlbm's kernels.
 from __future__ import annotations
 
 import time
-from typing import Callable, Dict, List, Sequence, Tuple
+from typing import Callable, Dict, Sequence, Tuple
 
 import numpy as np
 
