@@ -205,29 +205,40 @@ hipError_t launch_init(const InstDesc *d_desc, const InstDesc &h, int st, const 
 }
 
 // ------------------------------------------------------------------------
-// Window reduction: one thread per instance, fixed summation order
+// Window reduction: one workgroup per instance, fixed summation order
 // ------------------------------------------------------------------------
 
-__global__ void reduce_kernel(const double *partials, const int *pb, const int *pc, WindowState *ws, int ninst)
+__global__ void __launch_bounds__(256) reduce_kernel(const double *partials, const int *pb, const int *pc,
+                                                     WindowState *ws, int ninst)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ninst || pb[i] < 0) return;
+    const int i = blockIdx.x;                 // one workgroup per instance
+    if (i >= ninst || pb[i] < 0) return;      // uniform across the workgroup
+    __shared__ double sa[256], sb[256], sc[256];
+    const int t = threadIdx.x;
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int k = 0; k < pc[i]; ++k) {
+    for (int k = t; k < pc[i]; k += blockDim.x) {
         const double *p = partials + 3 * (size_t)(pb[i] + k);
         a += p[0]; b += p[1]; c += p[2];
     }
-    WindowState w = ws[i];
-    w.checks += 1;
-    w.residual = w.checks >= 2 ? sqrt(a) / sqrt(b) : -1.0;
-    if (c > 0.0) w.bad = 1;
-    ws[i] = w;
+    sa[t] = a; sb[t] = b; sc[t] = c;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {   // fixed order: bitwise reproducible
+        if (t < h) { sa[t] += sa[t + h]; sb[t] += sb[t + h]; sc[t] += sc[t + h]; }
+        __syncthreads();
+    }
+    if (t == 0) {
+        WindowState w = ws[i];
+        w.checks += 1;
+        w.residual = w.checks >= 2 ? sqrt(sa[0]) / sqrt(sb[0]) : -1.0;
+        if (sc[0] > 0.0) w.bad = 1;
+        ws[i] = w;
+    }
 }
 
 hipError_t launch_reduce(const double *partials, const int *pb, const int *pc, WindowState *ws, int ninst,
                          hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_kernel, dim3((ninst + 63) / 64), dim3(64), 0, s, partials, pb, pc, ws, ninst);
+    hipLaunchKernelGGL(reduce_kernel, dim3(ninst), dim3(256), 0, s, partials, pb, pc, ws, ninst);
     return hipGetLastError();
 }
 
