@@ -167,6 +167,26 @@ void destroy_graph(Batch *B)
 }
 
 // Tile queue of the active instances for the current block size.
+// Key of an instance's stochastic rounding: a hash of its description, so
+// that an instance rounds the same way alone and in any batch.
+uint32_t desc_salt(const mlbm_desc &d)
+{
+    uint32_t h = 0x3133u;
+    auto add = [&h](uint64_t v) {
+        h = mix32(h ^ (uint32_t)v);
+        h = mix32(h ^ (uint32_t)(v >> 32));
+    };
+    add((uint64_t)d.kind); add((uint64_t)d.n1); add((uint64_t)d.n2); add((uint64_t)d.n3);
+    add((uint64_t)d.walls); add((uint64_t)d.forcing_mode);
+    const double vals[5] = {d.tau, d.force, d.b, d.r_inner, d.width};
+    for (double x : vals) {
+        uint64_t u;
+        memcpy(&u, &x, sizeof(u));
+        add(u);
+    }
+    return h;
+}
+
 // The 16-bit storage formats keep a per-row reference table.
 bool uses_ref(int st) { return st == ST_F16 || st == ST_BF16; }
 
@@ -426,7 +446,7 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
             return bail(fail(MLBM_E_HIP, "hipMemsetAsync failed"));
         h.ref = nullptr;
         h.ctr = nullptr;
-        h.salt = mix32(0x3133u + (uint32_t)i);
+        h.salt = desc_salt(d);
         if (uses_ref(B->st)) {
             float *ref = nullptr;
             if (hipMalloc(&ref, sizeof(float) * 2 * Q * (size_t)h.n1) != hipSuccess)

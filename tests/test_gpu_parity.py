@@ -302,9 +302,14 @@ def test_instability_flag_from_planted_nan():
     assert bad
 
 
-def test_batch_graph_and_eager_are_bitwise_equal_to_single():
-    cases = [K.cylinder_case(0.95, 16, 4, 24, 0.7, De=De, walls3=True).replace(precision="f32", check_every=50)
-             for De in (10.0, 20.0, 30.0)]
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_batch_graph_and_eager_are_bitwise_equal_to_single(prec):
+    """Batched, graph-replayed and eager runs of the same instances agree bit
+    for bit, also for 16-bit storage (its stochastic rounding is keyed by the
+    instance description, node and step, not by the batch position)."""
+    # De up to 12 keeps the lattice Mach number below 0.4 on this small grid
+    cases = [K.cylinder_case(0.95, 16, 4, 24, 0.7, De=De, walls3=True).replace(precision=prec, check_every=50)
+             for De in (6.0, 9.0, 12.0)]
     inits = [K.perturbed_start(c, seed=7, amp=1e-2) for c in cases]
     b = mlbm.Batch(cases, inits)
     b.step(130)
@@ -316,12 +321,17 @@ def test_batch_graph_and_eager_are_bitwise_equal_to_single():
     e.set_launch(64, 0)
     e.step(130)
     for i in range(3):
+        assert np.all(np.isfinite(b[i].get_f()))
         assert np.array_equal(b[i].get_f(), e[i].get_f())
     assert b[1].residual() == single.residual()
 
 
-def test_persistent_grid_and_autotune_keep_results():
-    cases = [K.ellipsoid_case(20.0, R2, 24, 4, 48, 0.6, De=20.0, precision="f32") for R2 in (5.0, 10.0)]
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_persistent_grid_and_autotune_keep_results(prec):
+    """The autotuner restores the state it stepped (populations and, for
+    16-bit storage, the rounding step counter); a persistent grid gives the
+    same results as one workgroup per tile."""
+    cases = [K.ellipsoid_case(20.0, R2, 24, 4, 48, 0.6, De=20.0, precision=prec) for R2 in (5.0, 10.0)]
     a = mlbm.Batch(cases)
     a.step(40)
     b = mlbm.Batch(cases)
