@@ -35,6 +35,25 @@
  *   - the ellipsoidal slab is streamwise periodic with the metric frozen at
  *     theta = 0 and the printed (theta independent) Christoffel symbols.
  *
+ * Pins (tests that hold this code to facts fixed outside it):
+ *   - lattice: the printed Table I (tests/golden/table1_weights.txt), the
+ *     weights as the unique quadrature of the velocity set, isotropy through
+ *     sixth order and its failure at eighth;
+ *   - equilibrium and forcing: moments of f^eq equal the metric
+ *     Maxwell-Boltzmann moments, the flat limit equals the textbook third-order
+ *     Hermite equilibrium, forcing moments follow from integration by parts,
+ *     collision conserves mass and momentum, sigma enters through a2 only;
+ *   - geometry: Christoffels equal the Levi-Civita connection of the metric
+ *     and of the embedding, lattice rescaling, covariant force, streaming with
+ *     bounce-back is a permutation, hand-worked bounce-back paths;
+ *   - flow: uniform flow is a fixed point, a shear wave decays with
+ *     nu = cs2 (tau - 1/2), plane Poiseuille converges at second order, the
+ *     curved profile tends to its closed form, the mass budget closes each
+ *     step, the window residual of a single decaying mode equals
+ *     exp(lambda K) - 1;
+ *   - observables: vorticity and mean velocity of closed-form fields.
+ * Every function here has at least one such pin.
+ *
  * Precision: IEEE double throughout.  The per-node update is parallelised
  * over nodes with OpenMP; each node's arithmetic is the same with or without
  * threads, so results do not depend on the thread count.

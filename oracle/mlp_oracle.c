@@ -7,6 +7,11 @@
  * the mean-squared-error loss over the batch and the three outputs, its
  * gradient by backpropagation, and one Adam update (Kingma & Ba 2015).
  *
+ * Pins: the gradient against central differences of the loss, a network with
+ * zero parameters predicts zero, the forward pass of a one-hidden-layer
+ * network worked by hand, and the first Adam step in closed form
+ * (-lr sign(g) up to eps).
+ *
  * Parameter order: for each layer l = 0..depth, W_l as [n_out][n_in]
  * row-major, then b_l [n_out].
  */

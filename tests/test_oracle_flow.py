@@ -42,6 +42,27 @@ def test_shear_wave_decays_with_lattice_viscosity():
     assert abs(nu_meas / nu - 1) < 5e-3
 
 
+def test_window_residual_of_a_decaying_mode():
+    """Window residual R = |U_w - U_(w-1)| / |U_w| on a single shear-wave mode
+    decaying as exp(-lam t): every component scales by the same factor, so
+    R = exp(lam K) - 1 exactly. lam is measured independently from two
+    velocity snapshots K steps apart, before the residual is taken."""
+    n, tau, K_win = 32, 0.7, 100
+    case = K.Case(kind="flat", n1=n, n2=1, n3=1, walls=0, width=float(n), tau=tau)
+    x = np.arange(n) + 0.5
+    u = np.zeros((3, n, 1, 1))
+    u[1, :, 0, 0] = 1e-5 * np.sin(2 * math.pi * x / n)
+    S = O.Sim(case, init_u=u)
+    S.step(200)                                    # let the initial transient pass
+    a0 = np.linalg.norm(S.moments()[2][1])
+    S.step(K_win)
+    a1 = np.linalg.norm(S.moments()[2][1])
+    lam = math.log(a0 / a1) / K_win
+    R, steps, bad = S.run_until(0.0, K_win, 3 * K_win)   # tol 0: run all windows, keep the last R
+    assert not bad and steps == 3 * K_win
+    assert abs(R / (math.exp(lam * K_win) - 1.0) - 1.0) < 1e-6
+
+
 def _steady(case, tol=1e-10, max_steps=200000, init=None):
     S = O.Sim(case, init_u=K.poiseuille_field(case) if init is None else init)
     R, steps, bad = S.run_until(tol, 100, max_steps)
