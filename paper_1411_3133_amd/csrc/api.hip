@@ -449,7 +449,7 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
         h.salt = desc_salt(d);
         if (uses_ref(B->st)) {
             float *ref = nullptr;
-            if (hipMalloc(&ref, sizeof(float) * 2 * Q * (size_t)h.n1) != hipSuccess)
+            if (hipMalloc(&ref, sizeof(float) * Q * (size_t)h.n1) != hipSuccess)
                 return bail(fail(MLBM_E_OOM, "reference table allocation failed"));
             h.ref = ref;
             if (hipMalloc(&h.ctr, 2 * sizeof(uint32_t)) != hipSuccess)
@@ -922,7 +922,7 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
 
 // ---------------- checkpoints ---------------------------------------------
 
-static const char CK_MAGIC[8] = {'M', 'L', 'B', 'M', 'C', 'K', '0', '4'};
+static const char CK_MAGIC[8] = {'M', 'L', 'B', 'M', 'C', 'K', '0', '5'};
 
 mlbm_status mlbm_save(mlbm_handle h, const char *path)
 {
@@ -932,7 +932,7 @@ mlbm_status mlbm_save(mlbm_handle h, const char *path)
     const size_t N = (size_t)I->hd.N, sb = storage_bytes(B->st);
     std::vector<char> pops(sb * Q * N);
     std::vector<double> us(3 * N);
-    std::vector<float> ref(I->hd.ref ? (size_t)2 * Q * I->hd.n1 : 0);
+    std::vector<float> ref(I->hd.ref ? (size_t)Q * I->hd.n1 : 0);
     std::vector<WindowState> ws;
     mlbm_status s = read_ws(B, ws);
     if (s != MLBM_OK) return s;
@@ -981,7 +981,7 @@ mlbm_status mlbm_load(const char *path, void *hip_stream, mlbm_handle *out)
     const size_t N = (size_t)d.n1 * d.n2 * d.n3, sb = storage_bytes(d.precision);
     std::vector<char> pops(sb * Q * N);
     std::vector<double> us(3 * N);
-    std::vector<float> ref(uses_ref(d.precision) ? (size_t)2 * Q * d.n1 : 0);
+    std::vector<float> ref(uses_ref(d.precision) ? (size_t)Q * d.n1 : 0);
     uint32_t ctr = 0;
     ok = fread(pops.data(), 1, pops.size(), fp) == pops.size() && fread(us.data(), sizeof(double), us.size(), fp) == us.size() &&
          fread(ref.data(), sizeof(float), ref.size(), fp) == ref.size() &&

@@ -135,10 +135,9 @@ __device__ void init_offsets(const InstDesc &d, int n, const double *init_u, dou
 
 // Reference offsets of the 16-bit storage formats: per x1 row and
 // population, the row mean r of d = f/w - 1 of the initial state (table
-// [n1][41], followed by w r [n1][41] for decoding). Values
-// are stored as d - ref, which keeps the stored magnitudes (and so the
-// rounding error) small wherever the flow stays near its row mean. One
-// workgroup per row, fixed summation order.
+// [n1][41]). Values are stored as d - r, which keeps the stored magnitudes
+// (and so the rounding error) small wherever the flow stays near its row
+// mean. One workgroup per row, fixed summation order.
 __global__ void ref_kernel(const InstDesc *dd, const double *init_u, float *ref)
 {
     const InstDesc &d = *dd;
@@ -158,11 +157,7 @@ __global__ void ref_kernel(const InstDesc *dd, const double *init_u, float *ref)
             if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
             __syncthreads();
         }
-        if (threadIdx.x == 0) {
-            const float r = (float)(part[0] / d.P);
-            ref[x1 * Q + q] = r;
-            ref[(d.n1 + x1) * Q + q] = (float)wq(q) * r;   // w r, for decoding
-        }
+        if (threadIdx.x == 0) ref[x1 * Q + q] = (float)(part[0] / d.P);
         __syncthreads();
     }
 }
@@ -439,11 +434,11 @@ __global__ void step_nodes_kernel(const InstDesc *dd, int parity, const int64_t 
     if (n < 0 || n >= d.N) return;
     const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
     typename Codec<ST>::G g[Q];
-    gather_general<ST>(d.f[parity], d, x1, x2, x3, RefRow{d.ref, d.n1}, g);
+    gather_general<ST>(d.f[parity], d, x1, x2, x3, RefRow{d.ref}, g);
     NodeGeo<PAT, C> geo;
     geo.load(d.geo, d.geof, x1 * d.n3g + (d.n3g > 1 ? x3 : 0), d.n1 * d.n3g, (C)d.force);
     C rho, u[3];
-    collide<PAT, C, typename Codec<ST>::G>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
+    collide<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
     static_for<0, Q>([&](auto q) {
         // round through the storage format, as the step kernel stores it
         const float r = Codec<ST>::REF ? d.ref[x1 * Q + q] : 0.0f;
@@ -451,10 +446,10 @@ __global__ void step_nodes_kernel(const InstDesc *dd, int parity, const int64_t 
         // current counter (stochastic for the 16-bit formats)
         T tmp;
         if constexpr (Codec<ST>::REF)
-            tmp = Codec<ST>::encode_sr(g[q], (C)(1.0 / wq(q)), (C)r,
+            tmp = Codec<ST>::encode_sr(g[q], (C)r,
                                        RoundBits(d.salt, (uint32_t)n, d.ctr[parity]).template get<q>());
         else
-            tmp = Codec<ST>::encode(g[q], (C)(1.0 / wq(q)), (C)r);
+            tmp = Codec<ST>::encode(g[q], (C)r);
         out[k * Q + q] = Codec<ST>::to_f64(tmp, wq(q), (double)r) + wq(q);
     });
 }

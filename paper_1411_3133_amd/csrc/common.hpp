@@ -4,7 +4,8 @@
 //   populations  two buffers (pull: read one, write the other), each
 //                [41][n1][n2][n3] of the storage type, x3 fastest.  Stored
 //                values are offsets from the lattice weights: g = f - w_q
-//                for FP64/FP32, d = f / w_q - 1 for FP16/BF16.
+//                for FP64/FP32, d = f / w_q - 1 - r for FP16/BF16 (r: the
+//                row's reference offset of the population).
 //   geometry     FP64, structure of arrays [NGEO][n1][n3g] over the cross
 //                section (n3g = 1 when nothing depends on x3, e.g. the
 //                cylinder): Delta^ij = g^ij - delta^ij, Christoffels, unit
@@ -43,7 +44,7 @@ struct InstDesc {
     const double *geo;     // [NGEO][n1*n3g]
     const float *geof;     // the same geometry rounded to FP32 (read by FP32 arithmetic)
     double *usnap;         // [3][N]
-    const float *ref;      // FP16/BF16 storage: per-row reference r [n1][41], then w r [n1][41]; else null
+    const float *ref;      // FP16/BF16 storage: per-row reference r [n1][41]; else null
     uint32_t *ctr;         // FP16/BF16 storage: step counter [2] (read [parity], next in [parity ^ 1])
     uint32_t salt;         // per-instance key of the stochastic rounding
     int n1, n2, n3, walls;
@@ -119,19 +120,21 @@ __device__ __forceinline__ uint16_t float_to_f16_bits(float x) { return __half_a
 // low half always truncates -- measured on the part). Each rounding is
 // unbiased, so increments below the storage resolution (the per-step body
 // force, for one) are kept on average instead of being lost.
-typedef _Float16 mlbm_h2 __attribute__((ext_vector_type(2)));
-typedef __bf16 mlbm_b2 __attribute__((ext_vector_type(2)));
+// The builtins write one half of a register pair whose other half they
+// keep, which costs a register copy per conversion; only the low half is
+// stored here, so the instruction is issued directly with a fresh result
+// register (an arithmetic instruction: no memory access, no wait needed).
 __device__ __forceinline__ uint16_t float_to_f16_bits_sr(float x, uint32_t seed)
 {
-    const mlbm_h2 v = __builtin_amdgcn_cvt_sr_f16_f32(mlbm_h2{}, x, seed, false);
-    const _Float16 lo = v.x;
-    return __builtin_bit_cast(uint16_t, lo);
+    uint32_t v;
+    asm("v_cvt_sr_f16_f32 %0, %1, %2" : "=v"(v) : "v"(x), "v"(seed));
+    return (uint16_t)v;
 }
 __device__ __forceinline__ uint16_t float_to_bf16_bits_sr(float x, uint32_t seed)
 {
-    const mlbm_b2 v = __builtin_amdgcn_cvt_sr_bf16_f32(mlbm_b2{}, x, seed, false);
-    const __bf16 lo = v.x;
-    return __builtin_bit_cast(uint16_t, lo);
+    uint32_t v;
+    asm("v_cvt_sr_bf16_f32 %0, %1, %2" : "=v"(v) : "v"(x), "v"(seed));
+    return (uint16_t)v;
 }
 
 // 32-bit integer hash (xorshift-multiply, two rounds).
@@ -145,22 +148,24 @@ __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x)
     return x;
 }
 
-// T: stored type; C: compute type.  decode/encode map stored values to and
-// from the offset g = f - w (w = weight of the population). The 16-bit
-// formats store d = f/w - 1 - r, where r is the reference offset of the
-// population in the row the value is stored in (REF): decode takes
-// wr = w r and returns g = w d + wr, encode takes r. The wide formats ignore
-// the reference.
+// T: stored type; C: compute type; G: register type of the 41 populations.
+// In registers a population is the offset g = f - w (w = its weight) for the
+// wide formats, and the scaled offset h = f / w - 1 for the 16-bit formats
+// (SCALED). Those store d = h - r, where r is the reference offset of the
+// population in the row the value is stored in (REF): decode(v, r) gives the
+// register value, encode(x, r) the stored one; the wide formats ignore r.
+// to_f64 / from_f64 convert between stored values and FP64 offsets g.
 template <int ST> struct Codec;
 
 template <> struct Codec<ST_F64> {
     using T = double;
     using C = double;
-    using G = double;     // register type of the 41 populations
+    using G = double;
     static constexpr bool REF = false;
-    __device__ static __forceinline__ C decode(T v, C, C) { return v; }
-    __device__ static __forceinline__ T encode(C g, C, C) { return g; }
-    __device__ static __forceinline__ T encode_sr(C g, C, C, uint32_t) { return g; }
+    static constexpr bool SCALED = false;
+    __device__ static __forceinline__ C decode(T v, C) { return v; }
+    __device__ static __forceinline__ T encode(G g, C) { return g; }
+    __device__ static __forceinline__ T encode_sr(G g, C, uint32_t) { return g; }
     __device__ static __forceinline__ double to_f64(T v, double, double) { return v; }
     __device__ static __forceinline__ T from_f64(double g, double, double) { return g; }
 };
@@ -170,9 +175,10 @@ template <> struct Codec<ST_F32> {
     using C = float;
     using G = float;
     static constexpr bool REF = false;
-    __device__ static __forceinline__ C decode(T v, C, C) { return v; }
-    __device__ static __forceinline__ T encode(C g, C, C) { return g; }
-    __device__ static __forceinline__ T encode_sr(C g, C, C, uint32_t) { return g; }
+    static constexpr bool SCALED = false;
+    __device__ static __forceinline__ C decode(T v, C) { return v; }
+    __device__ static __forceinline__ T encode(G g, C) { return g; }
+    __device__ static __forceinline__ T encode_sr(G g, C, uint32_t) { return g; }
     __device__ static __forceinline__ double to_f64(T v, double, double) { return (double)v; }
     __device__ static __forceinline__ T from_f64(double g, double, double) { return (float)g; }
 };
@@ -182,9 +188,10 @@ template <> struct Codec<ST_F32D> {   // FP32 storage, FP64 collision, FP32 regi
     using C = double;
     using G = float;
     static constexpr bool REF = false;
-    __device__ static __forceinline__ G decode(T v, C, C) { return v; }
-    __device__ static __forceinline__ T encode(G g, C, C) { return g; }
-    __device__ static __forceinline__ T encode_sr(G g, C, C, uint32_t) { return g; }
+    static constexpr bool SCALED = false;
+    __device__ static __forceinline__ G decode(T v, C) { return v; }
+    __device__ static __forceinline__ T encode(G g, C) { return g; }
+    __device__ static __forceinline__ T encode_sr(G g, C, uint32_t) { return g; }
     __device__ static __forceinline__ double to_f64(T v, double, double) { return (double)v; }
     __device__ static __forceinline__ T from_f64(double g, double, double) { return (float)g; }
 };
@@ -194,12 +201,10 @@ template <> struct Codec<ST_F16> {
     using C = float;
     using G = float;
     static constexpr bool REF = true;
-    __device__ static __forceinline__ C decode(T v, C w, C wr) { return fmaf(f16_bits_to_float(v), w, wr); }
-    __device__ static __forceinline__ T encode(C g, C inv_w, C r) { return float_to_f16_bits(fmaf(g, inv_w, -r)); }
-    __device__ static __forceinline__ T encode_sr(C g, C inv_w, C r, uint32_t rnd)
-    {
-        return float_to_f16_bits_sr(fmaf(g, inv_w, -r), rnd);
-    }
+    static constexpr bool SCALED = true;
+    __device__ static __forceinline__ C decode(T v, C r) { return f16_bits_to_float(v) + r; }
+    __device__ static __forceinline__ T encode(G h, C r) { return float_to_f16_bits(h - r); }
+    __device__ static __forceinline__ T encode_sr(G h, C r, uint32_t rnd) { return float_to_f16_bits_sr(h - r, rnd); }
     __device__ static __forceinline__ double to_f64(T v, double w, double r)
     {
         return w * ((double)f16_bits_to_float(v) + r);
@@ -215,12 +220,10 @@ template <> struct Codec<ST_BF16> {
     using C = float;
     using G = float;
     static constexpr bool REF = true;
-    __device__ static __forceinline__ C decode(T v, C w, C wr) { return fmaf(bf16_bits_to_float(v), w, wr); }
-    __device__ static __forceinline__ T encode(C g, C inv_w, C r) { return float_to_bf16_bits(fmaf(g, inv_w, -r)); }
-    __device__ static __forceinline__ T encode_sr(C g, C inv_w, C r, uint32_t rnd)
-    {
-        return float_to_bf16_bits_sr(fmaf(g, inv_w, -r), rnd);
-    }
+    static constexpr bool SCALED = true;
+    __device__ static __forceinline__ C decode(T v, C r) { return bf16_bits_to_float(v) + r; }
+    __device__ static __forceinline__ T encode(G h, C r) { return float_to_bf16_bits(h - r); }
+    __device__ static __forceinline__ T encode_sr(G h, C r, uint32_t rnd) { return float_to_bf16_bits_sr(h - r, rnd); }
     __device__ static __forceinline__ double to_f64(T v, double w, double r)
     {
         return w * ((double)bf16_bits_to_float(v) + r);

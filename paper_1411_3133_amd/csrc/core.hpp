@@ -111,22 +111,27 @@ struct NodeGeo {
 // Collision
 // ------------------------------------------------------------------------
 
-// In-place BGK update of one node's offsets g[41] (Sec. II): on return g
-// holds f* - w.  rho_out and u_out receive rho' and the lattice velocity
+// In-place BGK update of one node's populations (Sec. II). g[q] holds the
+// offset f - w, or with SCALED the scaled offset (f - w) / w, before and
+// after the update. rho_out and u_out receive rho' and the lattice velocity
 // u = sum c f / rho' used by the collision (no half-force shift).  R is the
 // register type of the populations, C the arithmetic type (R may be
-// narrower: every value is widened to C before it is used).
-template <int PAT, class C, class R>
+// narrower: every value is widened to C before it is used). SCALED moves
+// the weights into the moment constants, so the update itself has none.
+template <int PAT, class C, class R, bool SCALED = false>
 __host__ __device__ __forceinline__ void collide(R (&g)[Q], const NodeGeo<PAT, C> &G, C omega, C kappa,
                                                  C &rho_out, C (&u_out)[3])
 {
+    // register value = ws(q) * (f - w) / w: ws is the weight for scaled
+    // registers, else 1
+    constexpr auto ws = [](int q) constexpr { return SCALED ? C(wq(q)) : C(1); };
     constexpr C cs2 = (C)CS2;
     constexpr C ics2 = (C)(1.0 / CS2);
     constexpr C ics4 = (C)(1.0 / (CS2 * CS2));
     constexpr C ics6 = (C)(1.0 / (CS2 * CS2 * CS2));
 
     // --- moments of the offsets
-    C m0 = (C)g[0];
+    C m0 = ws(0) * (C)g[0];
     C j[3] = {C(-0.0), C(-0.0), C(-0.0)};
     C p[3][3];
     static_for<0, 3>([&](auto I) { static_for<0, 3>([&](auto J) { p[I][J] = C(-0.0); }); });
@@ -135,13 +140,14 @@ __host__ __device__ __forceinline__ void collide(R (&g)[Q], const NodeGeo<PAT, C
         const C gp = (C)g[qp], gm = (C)g[qm];
         const C s = gp + gm;
         const C df = gp - gm;
-        m0 += s;
+        constexpr C wp = ws(qp);     // opposite populations share a weight
+        m0 += wp * s;
         static_for<0, 3>([&](auto I) {
             constexpr int ci = DIR[d][I] * k;
-            if constexpr (ci != 0) j[I] += C(ci) * df;
+            if constexpr (ci != 0) j[I] += (C(ci) * wp) * df;
             static_for<I, 3>([&](auto J) {
                 constexpr int cij = DIR[d][I] * DIR[d][J] * k * k;
-                if constexpr (cij != 0) p[I][J] += C(cij) * s;
+                if constexpr (cij != 0) p[I][J] += (C(cij) * wp) * s;
             });
         });
     });
@@ -198,8 +204,9 @@ __host__ __device__ __forceinline__ void collide(R (&g)[Q], const NodeGeo<PAT, C
     constexpr bool CONSERVE = sizeof(C) == 4;
     C dm = C(-0.0), dj[3] = {C(-0.0), C(-0.0), C(-0.0)};
     {
-        const R n0 = (R)(omw * (C)g[0] + C(W_REST) * baseE);
-        if constexpr (CONSERVE) dm += (C)n0 - (C)g[0];
+        constexpr C w0 = SCALED ? C(1) : C(W_REST);
+        const R n0 = (R)(omw * (C)g[0] + w0 * baseE);
+        if constexpr (CONSERVE) dm += ws(0) * ((C)n0 - (C)g[0]);
         g[0] = n0;
     }
 
@@ -266,17 +273,18 @@ __host__ __device__ __forceinline__ void collide(R (&g)[Q], const NodeGeo<PAT, C
                 const C ca2F = kf * (a2cFe - kk * a2cG);        // c . a2 . F
                 const C OF = Fc * (Q0 + half_ics6 * kk * ca2c) - ics4 * ca2F;
                 const C Od = Oeq + OF;
-                constexpr C w = C(wq(qp));
+                constexpr C w = SCALED ? C(1) : C(wq(qp));
                 const C te = w * Ev, to = w * Od;
                 const R np = (R)(omw * (C)g[qp] + (te + to));
                 const R nm = (R)(omw * (C)g[qm] + (te - to));
                 if constexpr (CONSERVE) {
+                    constexpr C wp = ws(qp);
                     const C dp = (C)np - (C)g[qp], dq = (C)nm - (C)g[qm];
-                    dm += dp + dq;
+                    dm += wp * (dp + dq);
                     const C dd = dp - dq;
                     static_for<0, 3>([&](auto I) {
                         constexpr int ci = DIR[Dd][I] * k;
-                        if constexpr (ci != 0) dj[I] += C(ci) * dd;
+                        if constexpr (ci != 0) dj[I] += (C(ci) * wp) * dd;
                     });
                 }
                 g[qp] = np;
@@ -301,7 +309,7 @@ __host__ __device__ __forceinline__ void collide(R (&g)[Q], const NodeGeo<PAT, C
             });
         });
         const C dm_exp = C(-2) * rho * (u[0] * tr[0] + u[1] * tr[1] + u[2] * tr[2]);
-        g[0] = (R)((C)g[0] + (dm_exp - dm));
+        g[0] = (R)((C)g[0] + (dm_exp - dm) * (C(1) / ws(0)));
         static_for<0, 3>([&](auto I) {
             C s = C(-0.0);
             if constexpr (Mask<PAT>::F(I)) s += rho * G.Fe[I];
@@ -316,7 +324,7 @@ __host__ __device__ __forceinline__ void collide(R (&g)[Q], const NodeGeo<PAT, C
                 });
                 s -= C(2) * tr[J] * MIJ;
             });
-            const C h = C(0.5) * (s - dj[I]);
+            const C h = (C(0.5) / ws(1 + 2 * I)) * (s - dj[I]);   // +-e_I share a weight
             g[1 + 2 * I] = (R)((C)g[1 + 2 * I] + h);
             g[2 + 2 * I] = (R)((C)g[2 + 2 * I] - h);
         });
@@ -405,30 +413,22 @@ struct RoundBits {
 };
 
 // Reference offsets of the 16-bit storage formats as a gather sees them.
-// The instance's table holds r [n1][41] followed by w r [n1][41]; a view
-// answers, for the source row `row` = x1 - t of a pull and a population q,
-// r (for encoding) and w r (for decoding).
+// The instance's table holds r [n1][41]; a view answers, for the source row
+// `row` = x1 - t of a pull and a population q, r.
 // RefScalar: for rows uniform across the wavefront (the step kernel's
 // gathers and store), read through the scalar cache; reads only.
 // RefRow: per-lane rows (auxiliary kernels).
 #define MLBM_CONST __attribute__((address_space(4)))
 struct RefScalar {
     const float *ref;
-    int n1;
     __device__ __forceinline__ float get_r(int, int row, int q) const
     {
         return ((const MLBM_CONST float *)ref)[__builtin_amdgcn_readfirstlane(row) * Q + q];
     }
-    __device__ __forceinline__ float get_wr(int, int row, int q) const
-    {
-        return ((const MLBM_CONST float *)ref)[(n1 + __builtin_amdgcn_readfirstlane(row)) * Q + q];
-    }
 };
 struct RefRow {
     const float *ref;
-    int n1;
     __device__ __forceinline__ float get_r(int, int row, int q) const { return ref[row * Q + q]; }
-    __device__ __forceinline__ float get_wr(int, int row, int q) const { return ref[(n1 + row) * Q + q]; }
 };
 
 struct LaneOffsets {
@@ -466,8 +466,8 @@ __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, 
     static_for<0, Q>([&](auto q) {
         constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
         const void *rowp = (const char *)src + rb[cslot(c1)] + (uint64_t)q * PS;
-        const C wr = Codec<ST>::REF ? (C)ref.get_wr(c1, rows[cslot(c1)], q) : C(0);
-        g[q] = Codec<ST>::decode(gload<T>(rowp, L.o2[cslot(c2)] + L.o3[cslot(c3)]), (C)wq(q), wr);
+        const C r = Codec<ST>::REF ? (C)ref.get_r(c1, rows[cslot(c1)], q) : C(0);
+        g[q] = Codec<ST>::decode(gload<T>(rowp, L.o2[cslot(c2)] + L.o3[cslot(c3)]), r);
     });
 }
 
@@ -511,7 +511,7 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
         constexpr int m = a1 > a2 ? (a1 > a3 ? a1 : a3) : (a2 > a3 ? a2 : a3);
         constexpr bool REF = Codec<ST>::REF;
         uint32_t off = rb[3 + c1] + (uint32_t)q * PS + L.o2[cslot(c2)] + L.o3[cslot(c3)];
-        C r = REF ? (C)ref.get_wr(c1, rows[3 + c1], q) : C(0);
+        C r = REF ? (C)ref.get_r(c1, rows[3 + c1], q) : C(0);
         if constexpr (c3 != 0) {
             constexpr int qo = opposite(q);
             constexpr int h1 = c1 / m, h2 = c2 / m, h3 = c3 / m;
@@ -520,21 +520,21 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
             if constexpr (m == 1) {
                 const uint32_t o0 = rb[3] + base + L.o2[2] + x3S;            // sb = 0: the node itself
                 off = dist == 0 ? o0 : off;
-                if constexpr (REF) r = dist == 0 ? (C)ref.get_wr(0, rows[3], qo) : r;
+                if constexpr (REF) r = dist == 0 ? (C)ref.get_r(0, rows[3], qo) : r;
             } else {
                 const uint32_t oa = rb[3 - 2 * h1] + base + o2t[3 - 2 * h2] + (uint32_t)((int)x3S + 2 * h3 * (int)S);
                 const uint32_t ob = rb[3] + base + L.o2[2] + x3S;
                 const uint32_t oc = rb[3 + 2 * h1] + base + o2t[3 + 2 * h2] + (uint32_t)((int)x3S - 2 * h3 * (int)S);
                 off = dist == 0 ? oa : (dist == 1 ? ob : (dist == 2 ? oc : off));
                 if constexpr (REF) {
-                    const C ra = (C)ref.get_wr(-2 * h1, rows[3 - 2 * h1], qo);
-                    const C rbv = (C)ref.get_wr(0, rows[3], qo);
-                    const C rc = (C)ref.get_wr(2 * h1, rows[3 + 2 * h1], qo);
+                    const C ra = (C)ref.get_r(-2 * h1, rows[3 - 2 * h1], qo);
+                    const C rbv = (C)ref.get_r(0, rows[3], qo);
+                    const C rc = (C)ref.get_r(2 * h1, rows[3 + 2 * h1], qo);
                     r = dist == 0 ? ra : (dist == 1 ? rbv : (dist == 2 ? rc : r));
                 }
             }
         }
-        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)off), (C)wq(q), r);
+        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)off), r);
     });
 }
 
@@ -587,8 +587,8 @@ __device__ __forceinline__ void gather_x1wall(const void *src, const InstDesc &d
                 inrow = (k2 == 0 ? o2s[0] : (k2 == 1 ? o2s[1] : o2s[2])) + (k3 == 0 ? o3s[0] : (k3 == 1 ? o3s[1] : o3s[2]));
             }
         }
-        const C r = Codec<ST>::REF ? (C)ref.get_wr(x1 - srow, srow, splane) : C(0);
-        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(rowoff + inrow)), (C)wq(q), r);
+        const C r = Codec<ST>::REF ? (C)ref.get_r(x1 - srow, srow, splane) : C(0);
+        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(rowoff + inrow)), r);
     });
 }
 
@@ -661,9 +661,9 @@ __device__ __forceinline__ void gather_general(const void *src, const InstDesc &
         const int col = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip, row);
         const uint32_t qs = flip ? (uint32_t)qo : (uint32_t)q;
         const uint32_t e = ((uint32_t)row * (uint32_t)Q + qs) * (uint32_t)d.P + (uint32_t)col;
-        C wr = C(0);
-        if constexpr (Codec<ST>::REF) wr = (C)RefRow{d.ref, d.n1}.get_wr(0, row, (int)qs);   // per-lane row
-        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(e * S)), (C)wq(q), wr);
+        C r = C(0);
+        if constexpr (Codec<ST>::REF) r = (C)RefRow{d.ref}.get_r(0, row, (int)qs);   // per-lane row
+        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(e * S)), r);
     });
 }
 

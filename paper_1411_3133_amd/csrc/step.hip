@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
         const void *src = d.f[a.parity];
         void *dst = d.f[a.parity ^ 1];
         constexpr uint32_t S = sizeof(T);
-        const RefScalar R{d.ref, d.n1};
+        const RefScalar R{d.ref};
         uint32_t ctr = 0;                      // step counter of the stochastic rounding
         if constexpr (Codec<ST>::REF) {
             ctr = gload<uint32_t>(d.ctr, 4ull * (uint32_t)a.parity);
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
             NodeGeo<PAT, C> geo;
             geo.load(d.geo, d.geof, gidx, d.n1 * d.n3g, (C)d.force);
             C rho, u[3];
-            collide<PAT, C, typename Codec<ST>::G>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
+            collide<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
             const size_t n = (size_t)x1 * d.P + col;
             void *drow = (char *)dst + pop_elem(0, x1, 0, d.P) * S;
             const uint32_t loff = (uint32_t)col * S;
@@ -88,12 +88,12 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
                 static_for<0, Q>([&](auto q) {
                     void *plane = (char *)drow + (uint64_t)q * (uint64_t)d.P * S;
                     gstore_nt<T>(plane, loff,
-                                 Codec<ST>::encode_sr(g[q], (C)(1.0 / wq(q)), (C)R.get_r(0, x1, q), rb.template get<q>()));
+                                 Codec<ST>::encode_sr(g[q], (C)R.get_r(0, x1, q), rb.template get<q>()));
                 });
             } else {
                 static_for<0, Q>([&](auto q) {
                     void *plane = (char *)drow + (uint64_t)q * (uint64_t)d.P * S;
-                    gstore_nt<T>(plane, loff, Codec<ST>::encode(g[q], (C)(1.0 / wq(q)), C(0)));
+                    gstore_nt<T>(plane, loff, Codec<ST>::encode(g[q], C(0)));
                 });
             }
             if constexpr (CHECK) {
