@@ -129,7 +129,7 @@ def time_to_steady(n_train, n_test, tol=1e-6, cap=150000):
 
 
 def uneven_batch_leg(precision, steps=1000, warmup=200):
-    """Throughput of the persistent kernel on the uneven config-4 batch: 64
+    """Throughput of the persistent kernel on the uneven ellipsoid batch: 64
     double-curved instances of 8 curvature pairs (N_r 45..96, N_phi 64..240,
     2.9 M nodes), one launch per step over all of them, autotuned launch,
     HIP-event time per step on the batch stream."""
@@ -137,7 +137,7 @@ def uneven_batch_leg(precision, steps=1000, warmup=200):
     from paper_1411_3133_amd import cases as K
     from paper_1411_3133_amd import mlbm
 
-    cases = K.config4_batch(precision=precision)
+    cases = K.uneven_ellipsoid_batch(precision=precision)
     inits = [K.perturbed_start(c, seed=3133 + i, amp=1e-4) for i, c in enumerate(cases)]
     b = mlbm.Batch(cases, inits, stream=torch.cuda.current_stream())
     block, grid = b.autotune(steps=10)
@@ -151,7 +151,7 @@ def uneven_batch_leg(precision, steps=1000, warmup=200):
     nodes = sum(c.N for c in cases)
     b.close()
     alg = 2 * 41 * BYTES[precision] * nodes
-    return {"workload": "config4 batch: 64 ellipsoid slabs, 8 curvature pairs (R2/R1 0.25..4, N_r 45..96, "
+    return {"workload": "uneven ellipsoid batch: 64 ellipsoid slabs, 8 curvature pairs (R2/R1 0.25..4, N_r 45..96, "
                         "N_phi 64..240), De 20..200, 1e-4 perturbation",
             "nodes": nodes, "storage": precision, "launch": {"block": block, "grid": grid},
             "MLUPS": round(nodes * steps / wall / 1e6, 1),
@@ -217,7 +217,7 @@ def main():
                     help="unseen cases in the time-to-steady leg (0 skips it)")
     ap.add_argument("--steady-train", type=int, default=64, help="training fields for the warm start")
     ap.add_argument("--critical", type=int, default=1, help="run the critical-De leg (0 skips it)")
-    ap.add_argument("--uneven", type=int, default=1, help="time the uneven config-4 batch (0 skips it)")
+    ap.add_argument("--uneven", type=int, default=1, help="time the uneven ellipsoid batch (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -243,7 +243,7 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    cases = K.config2_sweep(precision=args.precision)
+    cases = K.cylinder_sweep(precision=args.precision)
     inits = [K.perturbed_start(c, seed=1411 + i, amp=1e-4) for i, c in enumerate(cases)]
     batch = mlbm.Batch(cases, inits, stream=stream)
     nodes = sum(c.N for c in cases)
@@ -271,7 +271,7 @@ def main():
     alg_bytes = 2 * 41 * S * nodes
     achieved = alg_bytes / (ev_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
-    tag = f"config2_sweep_{args.precision}"
+    tag = f"cylinder_sweep_64x4x256_{args.precision}"
     traffic = measured_traffic(tag, digest)
     line = {
         "metric": "MLUPS & % HBM peak; time-to-steady per case, warm/batched vs plain at 1e-6",
@@ -287,7 +287,7 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {
-            "workload": "config2 sweep: curved channel (cylinder) 64x4x256, eta=0.975, end walls, "
+            "workload": "curved-channel sweep: cylinder 64x4x256, eta=0.975, end walls, "
                         "De=30..60 (31 instances), laminar start + 1e-4 perturbation",
             "instances": len(cases), "nodes": nodes, "storage": args.precision,
             "tau": cases[0].tau, "check_every": cases[0].check_every,

@@ -255,13 +255,13 @@ def ellipsoid_case(R1: float, R2: float, n1: int, n2: int, n3: int, tau: float,
     return c
 
 
-def config1(precision: str = "f64") -> Case:
+def laminar_cylinder(precision: str = "f64") -> Case:
     """Curved channel, cylindrical coordinates: 16 x 4 x 32, eta = 0.9, tau = 0.8,
     De = 20, rest start, 2000 steps."""
-    return cylinder_case(0.9, 16, 4, 32, 0.8, De=20.0, precision=precision, label="C1")
+    return cylinder_case(0.9, 16, 4, 32, 0.8, De=20.0, precision=precision, label="cyl16-De20")
 
 
-def config2_sweep(precision: str = "f32", De_values=None) -> List[Case]:
+def cylinder_sweep(precision: str = "f32", De_values=None) -> List[Case]:
     """Curved channel near transition: 64 x 4 x 256, eta = 0.975, z end walls,
     De swept 30..60 by body force, tau from the Mach rule at De = 60."""
     if De_values is None:
@@ -270,20 +270,20 @@ def config2_sweep(precision: str = "f32", De_values=None) -> List[Case]:
     width = (1.0 - eta) / eta
     tau = round(tau_for_mach(64, 60.0, width, 1.0), 4)
     return [cylinder_case(eta, 64, 4, 256, tau, De=De, walls3=True, precision=precision,
-                          label=f"C2-De{De:g}") for De in De_values]
+                          label=f"cyl64-De{De:g}") for De in De_values]
 
 
-def config3_cases(precision: str = "f16", De: float = 60.0) -> List[Case]:
+def ellipsoid_96x192_cases(precision: str = "f16", De: float = 60.0) -> List[Case]:
     """Double-curved channel: 96 x 4 x 192, R1/d = 20, R2/d in {5, 10, 20, 40}."""
     out = []
     for R2 in (5.0, 10.0, 20.0, 40.0):
         tau = round(tau_for_mach(96, 150.0, 1.0, 20.0), 4)
         out.append(ellipsoid_case(20.0, R2, 96, 4, 192, tau, De=De, precision=precision,
-                                  label=f"C3-R2_{R2:g}"))
+                                  label=f"ell96-R2_{R2:g}"))
     return out
 
 
-def config4_batch(seed: int = 3133, n_pairs: int = 8, per_pair: int = 8,
+def uneven_ellipsoid_batch(seed: int = 3133, n_pairs: int = 8, per_pair: int = 8,
                   precision: str = "f32", De_lo: float = 20.0, De_hi: float = 200.0,
                   n3_multiple: int = 16) -> List[Case]:
     """Batched sweep: curvature pairs with R2/R1 log-uniform in [0.25, 4]
@@ -303,7 +303,7 @@ def config4_batch(seed: int = 3133, n_pairs: int = 8, per_pair: int = 8,
         tau = round(tau_for_mach(n1, max(Des), 1.0, R1), 4)
         for k, De in enumerate(Des):
             cases.append(ellipsoid_case(R1, R2, n1, 4, n3, tau, De=De, precision=precision,
-                                        label=f"C4-p{p}-k{k}"))
+                                        label=f"pair{p}-k{k}"))
     return cases
 
 
@@ -332,7 +332,7 @@ def warmstart_cases(n: int, seed: int, n1: int = 24, n3: int = 48, ratio_lo: flo
 
 def critical_pairs(seed: int = 3133, n1: int = 32, De_max: float = 80.0, min_R2: float = 18.0,
                    precision: str = "f64", n_pairs: int = 8):
-    """Curvature pairs of the batched sweep (config4_batch with the same
+    """Curvature pairs of the batched sweep (uneven_ellipsoid_batch with the same
     seed) for the critical-De study: pairs with R2/d >= min_R2 (the scheme's
     stable range at this tau), each at n1 x 4 x n3 with the pair's
     cross-section aspect n3/n1 kept (n3 rounded to a multiple of 4, >= 8),
@@ -351,8 +351,8 @@ def critical_pairs(seed: int = 3133, n1: int = 32, De_max: float = 80.0, min_R2:
 
         def make(De, R2=R2, n3=n3, p=p):
             return ellipsoid_case(20.0, R2, n1, 4, n3, tau, De=float(De), precision=precision,
-                                  label=f"C4-p{p}")
-        out.append((f"C4-p{p}", make))
+                                  label=f"pair{p}")
+        out.append((f"pair{p}", make))
     return out
 
 

@@ -56,7 +56,7 @@ def test_kernel_streaming_fold_equals_oracle_pull_map(n1, n2, n3, walls):
 
 
 def test_kernel_streaming_fold_at_benchmark_sizes():
-    for case in (K.config1(), K.config2_sweep(De_values=[40.0])[0], K.config3_cases()[0]):
+    for case in (K.laminar_cylinder(), K.cylinder_sweep(De_values=[40.0])[0], K.ellipsoid_96x192_cases()[0]):
         src, sq = mlbm.pull_map(case)
         assert src.min() >= 0 and src.max() < case.N
         flat = src * 41 + sq
@@ -69,10 +69,10 @@ def test_kernel_streaming_fold_at_benchmark_sizes():
     dict(kind="ellipsoid", b=0.0), dict(kind="ellipsoid", n3=4000, b=1.0),
 ])
 def test_invalid_descriptions_are_rejected_before_any_device_work(bad):
-    case = K.config1()
+    case = K.laminar_cylinder()
     for k, v in bad.items():
         setattr(case, k, v)
-    d, _ = mlbm.make_desc(case) if "forcing_mode" not in bad else mlbm.make_desc(K.config1())
+    d, _ = mlbm.make_desc(case) if "forcing_mode" not in bad else mlbm.make_desc(K.laminar_cylinder())
     if "forcing_mode" in bad:
         d.forcing_mode = 2
     import ctypes as C

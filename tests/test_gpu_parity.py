@@ -5,7 +5,7 @@ Tolerances
   FP64 storage and collision: rounding only.  Both sides round differently
   (pairwise versus tensor form), every step adds ~1e-16 relative per
   population and BGK is contractive, so 1e-13 (tiny grids, <= 60 steps) and
-  1e-12 (config 1, 2000 steps) of max |f| bound the difference.
+  1e-12 (laminar cylinder 16 x 4 x 32, 2000 steps) of max |f| bound the difference.
   FP32: 1e-5 relative L2 on the velocity (the target stated for the path).
   FP16 / BF16 offset storage: 1e-3 relative L2 on the velocity target; the
   sampled one-step checks bound each population by the storage rounding of
@@ -91,16 +91,16 @@ def test_fp64_general_pattern_kernel_matches_oracle(monkeypatch):
 
 
 @pytest.fixture(scope="module")
-def config1_oracle():
-    case = K.config1()
+def laminar_cylinder_oracle():
+    case = K.laminar_cylinder()
     o = O.Sim(case)
     o.step(2000)
     rho, u, _ = o.moments()
     return case, o.get_f(), rho, u, o.observables()
 
 
-def test_config1_fp64_matches_oracle(config1_oracle):
-    case, f_o, rho_o, u_o, obs_o = config1_oracle
+def test_laminar_cylinder_fp64_matches_oracle(laminar_cylinder_oracle):
+    case, f_o, rho_o, u_o, obs_o = laminar_cylinder_oracle
     g = mlbm.Sim(case.replace(precision="f64"))
     g.step(2000)
     assert _rel_max(g.get_f(), f_o) < 1e-12
@@ -113,13 +113,13 @@ def test_config1_fp64_matches_oracle(config1_oracle):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f32c64"])
-def test_config1_fp32_velocity_error(config1_oracle, prec):
-    case, f_o, rho_o, u_o, obs_o = config1_oracle
+def test_laminar_cylinder_fp32_velocity_error(laminar_cylinder_oracle, prec):
+    case, f_o, rho_o, u_o, obs_o = laminar_cylinder_oracle
     g = mlbm.Sim(case.replace(precision=prec))
     g.step(2000)
     rho, u = g.moments()
     err = _rel_l2(u, u_o)
-    print(f"config1 {prec}: velocity rel L2 {err:.3e}")
+    print(f"laminar cylinder {prec}: velocity rel L2 {err:.3e}")
     assert err < 1e-6
 
 
@@ -164,13 +164,13 @@ def test_reduced_precision_velocity_and_dean_error(ellipsoid_oracle, prec):
 # than one unit in the last place, which for stored magnitudes below 4 is
 # 2^-8 (binary16) and 2^-5 (bfloat16).
 @pytest.mark.parametrize("prec,bound", [("f16", 1e-3), ("bf16", 2e-3)])
-def test_reduced_precision_long_run_config2(prec, bound):
-    """Config-2 instance (De = 45, 64 x 4 x 256, end walls) for 10 000 steps:
+def test_reduced_precision_long_run_cylinder_sweep(prec, bound):
+    """Curved-channel sweep instance (De = 45, 64 x 4 x 256, end walls) for 10 000 steps:
     16-bit storage against FP64 storage on the GPU (which matches the oracle
     to 1e-12 elsewhere). Stochastic rounding keeps the per-step force
     increments that round-to-nearest loses (0.9 % Dean-number bias at 60 000
     steps without it); measured 1.7e-4 (FP16) and 6.8e-4 (BF16)."""
-    case = K.config2_sweep(De_values=[45.0])[0]
+    case = K.cylinder_sweep(De_values=[45.0])[0]
     init = K.perturbed_start(case, seed=1, amp=1e-3)
     sims = {p: mlbm.Sim(case.replace(precision=p), init_u=init) for p in ("f64", prec)}
     for s in sims.values():
@@ -179,16 +179,16 @@ def test_reduced_precision_long_run_config2(prec, bound):
     _, u = sims[prec].moments()
     err = _rel_l2(u, u64)
     de_err = abs(sims[prec].vortex_intensity()[2] / sims["f64"].vortex_intensity()[2] - 1)
-    print(f"config2 {prec} 10k steps: velocity rel L2 {err:.3e}, De {de_err:.2e}")
+    print(f"cylinder 64x4x256 {prec} 10k steps: velocity rel L2 {err:.3e}, De {de_err:.2e}")
     assert err < bound and de_err < bound
 
 
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f16", 2.0 ** -8), ("bf16", 2.0 ** -5)])
 def test_sampled_one_step_at_full_size(prec, tol):
-    """Config-2 size (64 x 4 x 256, end walls): after 150 GPU steps, one more
+    """Curved-channel sweep size (64 x 4 x 256, end walls): after 150 GPU steps, one more
     step of sampled nodes (corners, walls, interior) against the oracle
     applied to the GPU's own decoded state."""
-    case = K.config2_sweep(precision=prec, De_values=[45.0])[0]
+    case = K.cylinder_sweep(precision=prec, De_values=[45.0])[0]
     init = K.perturbed_start(case, seed=1411, amp=1e-2)
     g = mlbm.Sim(case, init_u=init)
     g.step(150)
@@ -206,19 +206,19 @@ def test_sampled_one_step_at_full_size(prec, tol):
     assert err < tol
 
 
-@pytest.mark.parametrize("workload", ["config2", "config4"])
+@pytest.mark.parametrize("workload", ["cylinder_sweep", "uneven_ellipsoid_batch"])
 def test_batched_step_kernel_at_full_size(workload):
     """The autotuned batched step kernel (the launch bench.py times) on the
-    full config-2 sweep (31 instances) and the uneven config-4 batch (64
+    full curved-channel sweep (31 instances) and the uneven ellipsoid batch (64
     instances, 2.9 M nodes): after 150 steps, one more step; the stored
     populations of sampled nodes (walls, corners, interior) of three
     instances of different shapes match the FP64 oracle applied to the
     pre-step state, to FP32 rounding."""
-    if workload == "config2":
-        cases = K.config2_sweep(precision="f32")
+    if workload == "cylinder_sweep":
+        cases = K.cylinder_sweep(precision="f32")
         picks = [0, 15, 30]
     else:
-        cases = K.config4_batch(precision="f32")
+        cases = K.uneven_ellipsoid_batch(precision="f32")
         picks = [0, 44, 55]          # pairs 0, 5, 6: different n1, n3 and tau
     inits = [K.perturbed_start(c, seed=1411 + i, amp=1e-2) for i, c in enumerate(cases)]
     b = mlbm.Batch(cases, inits)
@@ -243,13 +243,13 @@ def test_batched_step_kernel_at_full_size(workload):
 
 
 @pytest.mark.parametrize("prec,tol", [("f16", 2.0 ** -8), ("bf16", 2.0 ** -5)])
-def test_config3_16bit_step_kernel_at_full_size(prec, tol):
-    """Config-3 shape (ellipsoid 96 x 4 x 192, R1/d = 20, R2/d = 40) in 16-bit
+def test_ellipsoid_96x192_16bit_step_kernel_at_full_size(prec, tol):
+    """Double-curved channel (ellipsoid 96 x 4 x 192, R1/d = 20, R2/d = 40) in 16-bit
     storage: after 150 steps, one more step of the step kernel; sampled
     stored populations (walls and interior) match the FP64 oracle applied to
     the decoded pre-step state within one unit in the last place of the
     16-bit format (stored magnitudes below 4)."""
-    case = [c for c in K.config3_cases(precision=prec) if abs(c.r_inner - 40.0) < 1e-9][0]
+    case = [c for c in K.ellipsoid_96x192_cases(precision=prec) if abs(c.r_inner - 40.0) < 1e-9][0]
     init = K.perturbed_start(case, seed=7, amp=1e-2)
     g = mlbm.Sim(case, init_u=init)
     g.step(150)
@@ -264,7 +264,7 @@ def test_config3_16bit_step_kernel_at_full_size(prec, tol):
     ref = O.Sim(case.replace(precision="f64")).step_nodes(state, nodes)
     _, w, _, _ = O.lattice()
     err = (np.abs(new[:, nodes].T - ref) / w[None, :]).max()
-    print(f"config3 R2/d=40 {prec}: max |df|/w = {err:.3e}")
+    print(f"ellipsoid 96x192 R2/d=40 {prec}: max |df|/w = {err:.3e}")
     assert err < tol
     g.close()
 

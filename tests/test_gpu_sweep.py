@@ -17,7 +17,7 @@ def _mid(x):
 
 
 def test_critical_dean_plain_and_warm_agree():
-    pairs = [p for p in K.critical_pairs(n1=24, De_max=60.0, min_R2=20.0) if p[0] in ("C4-p0", "C4-p6")]
+    pairs = [p for p in K.critical_pairs(n1=24, De_max=60.0, min_R2=20.0) if p[0] in ("pair0", "pair6")]
     assert len(pairs) == 2
     grid = [25.0, 30.0, 35.0, 40.0, 45.0, 50.0]
     kw = dict(ks=(2, 4), tol=1e-7, max_steps=300000, train_steps=((3000, 2e-3), (2000, 5e-4)))

@@ -120,11 +120,11 @@ def test_improved_forcing_beats_old_forcing(curved_errors):
     assert curved_errors[(0.9, 1)] > 1.5 * curved_errors[(0.9, 0)]
 
 
-def test_config1_profile_and_dean_number():
-    """Config 1 as specified (16 x 4 x 32, eta = 0.9, tau = 0.8, De = 20, rest
+def test_laminar_cylinder_profile_and_dean_number():
+    """Laminar curved channel (cylinder 16 x 4 x 32, eta = 0.9, tau = 0.8, De = 20, rest
     start, 2000 steps): profile within 3 % of the closed form and De within 3 %
     (Mach number about 0.7 at this resolution)."""
-    case = K.config1()
+    case = K.laminar_cylinder()
     S = O.Sim(case)
     S.step(2000)
     r = K.node_coords(case)[0]
