@@ -159,6 +159,38 @@ def uneven_batch_leg(precision, steps=1000, warmup=200):
             "frac": round(alg / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def beyond_cache_leg(precision, steps=500, warmup=100):
+    """Step-kernel throughput on one instance whose population buffers are 4.5x
+    (FP32, FP16/BF16) or 9x (FP64) the 256 MB last-level cache: ellipsoid
+    96 x 192 cross-section with 192 slabs (384 for 16-bit storage). The
+    sweep workloads partly fit in that cache; this one cannot."""
+    import torch
+    from paper_1411_3133_amd import cases as K
+    from paper_1411_3133_amd import mlbm
+
+    case = K.beyond_cache_case(precision)
+    b = mlbm.Batch([case], [K.perturbed_start(case, seed=96, amp=1e-4)], stream=torch.cuda.current_stream())
+    block, grid = b.autotune(steps=10)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = b.last_step_ms()
+    bad = b[0].residual()[1]
+    b.close()
+    alg = 2 * 41 * BYTES[precision] * case.N
+    return {"workload": f"ellipsoid 96x{case.n2}x192 (R1/d=20, R2/d=40, De=60), one instance, "
+                        f"1e-4 perturbation",
+            "nodes": case.N, "storage": precision, "buffers_MB": round(alg / 1e6, 1),
+            "launch": {"block": block, "grid": grid},
+            "MLUPS": round(case.N * steps / wall / 1e6, 1),
+            "achieved_GBs": round(alg / (ev_ms * 1e-3) / 1e9, 1),
+            "frac": round(alg / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "unstable": bool(bad)}
+
+
 def critical_dean_leg(tol=1e-7):
     """Critical Dean numbers (onset of 2, 4 and 6 cells) of the stable
     curvature pairs of the batched sweep, at N_r = 32, by batched bisection to
@@ -218,6 +250,8 @@ def main():
     ap.add_argument("--steady-train", type=int, default=64, help="training fields for the warm start")
     ap.add_argument("--critical", type=int, default=1, help="run the critical-De leg (0 skips it)")
     ap.add_argument("--uneven", type=int, default=1, help="time the uneven ellipsoid batch (0 skips it)")
+    ap.add_argument("--beyond-cache", type=int, default=1,
+                    help="time one instance larger than the last-level cache (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -310,6 +344,8 @@ def main():
     batch.close()
     if args.uneven:
         line["uneven_batch"] = uneven_batch_leg(args.precision)
+    if args.beyond_cache:
+        line["beyond_cache"] = beyond_cache_leg(args.precision)
     if args.steady > 0:
         line["time_to_steady"] = time_to_steady(args.steady_train, args.steady)
     if args.critical:

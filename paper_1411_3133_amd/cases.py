@@ -283,6 +283,19 @@ def ellipsoid_96x192_cases(precision: str = "f16", De: float = 60.0) -> List[Cas
     return out
 
 
+def beyond_cache_case(precision: str = "f32", n2: Optional[int] = None) -> Case:
+    """One double-curved channel large enough that its two population buffers
+    are several times the GPU's 256 MB last-level cache: the 96 x 192
+    ellipsoid cross-section (R1/d = 20, R2/d = 40) with 192 streamwise slabs
+    (3.5 M nodes) for 4- and 8-byte storage, 384 slabs (7.1 M nodes) for
+    2-byte storage, so every step streams its populations from HBM."""
+    if n2 is None:
+        n2 = 384 if precision in ("f16", "bf16") else 192
+    tau = round(tau_for_mach(96, 150.0, 1.0, 20.0), 4)
+    return ellipsoid_case(20.0, 40.0, 96, n2, 192, tau, De=60.0, precision=precision,
+                          label=f"ell96-R2_40-slabs{n2}")
+
+
 def uneven_ellipsoid_batch(seed: int = 3133, n_pairs: int = 8, per_pair: int = 8,
                   precision: str = "f32", De_lo: float = 20.0, De_hi: float = 200.0,
                   n3_multiple: int = 16) -> List[Case]:
