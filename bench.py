@@ -159,7 +159,7 @@ def uneven_batch_leg(precision, steps=1000, warmup=200):
             "frac": round(alg / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def beyond_cache_leg(precision, steps=500, warmup=100):
+def beyond_cache_leg(precision, steps=500, warmup=100, block=0, grid=0):
     """Step-kernel throughput on one instance whose population buffers are 4.5x
     (FP32, FP16/BF16) or 9x (FP64) the 256 MB last-level cache: ellipsoid
     96 x 192 cross-section with 192 slabs (384 for 16-bit storage). The
@@ -170,7 +170,10 @@ def beyond_cache_leg(precision, steps=500, warmup=100):
 
     case = K.beyond_cache_case(precision)
     b = mlbm.Batch([case], [K.perturbed_start(case, seed=96, amp=1e-4)], stream=torch.cuda.current_stream())
-    block, grid = b.autotune(steps=10)
+    if block:
+        b.set_launch(block, grid)
+    else:
+        block, grid = b.autotune(steps=10)
     b.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -345,7 +348,7 @@ def main():
     if args.uneven:
         line["uneven_batch"] = uneven_batch_leg(args.precision)
     if args.beyond_cache:
-        line["beyond_cache"] = beyond_cache_leg(args.precision)
+        line["beyond_cache"] = beyond_cache_leg(args.precision, block=args.block, grid=args.grid)
     if args.steady > 0:
         line["time_to_steady"] = time_to_steady(args.steady_train, args.steady)
     if args.critical:
