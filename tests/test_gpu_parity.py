@@ -269,6 +269,35 @@ def test_ellipsoid_96x192_16bit_step_kernel_at_full_size(prec, tol):
     g.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f16", 2.0 ** -8)])
+def test_beyond_cache_step_kernel_at_full_size(prec, tol):
+    """The instance bench.py's beyond-cache leg times (ellipsoid 96 x 192
+    cross-section, 192 slabs in FP32 and 384 in FP16: 3.5 M and 7.1 M nodes,
+    the largest population offsets the kernels address), in the autotuned
+    launch: after 100 steps, one more step; sampled stored populations
+    (walls, the last slab and interior) match the FP64 oracle applied to the
+    decoded pre-step state."""
+    case = K.beyond_cache_case(prec)
+    b = mlbm.Batch([case], [K.perturbed_start(case, seed=96, amp=1e-2)])
+    b.autotune(steps=5)
+    b.step(100)
+    state = b[0].get_f()
+    b.step(1)
+    new = b[0].get_f().reshape(41, -1)
+    b.close()
+    rng = np.random.default_rng(11)
+    n1, n2, n3 = case.n1, case.n2, case.n3
+    edges = [((x1 * n2 + x2) * n3 + x3) for x1 in (0, 1, 2, n1 - 3, n1 - 1) for x2 in (0, 1, n2 - 1)
+             for x3 in (0, 1, n3 // 2, n3 - 2, n3 - 1)]
+    nodes = np.unique(np.concatenate([edges, rng.integers(0, case.N, 300)]))
+    ref = O.Sim(case.replace(precision="f64")).step_nodes(state, nodes)
+    del state
+    _, w, _, _ = O.lattice()
+    err = (np.abs(new[:, nodes].T - ref) / w[None, :]).max()
+    print(f"beyond-cache {n1}x{n2}x{n3} {prec}: max |df|/w = {err:.3e}")
+    assert err < tol
+
+
 def test_window_residual_matches_oracle():
     case = K.cylinder_case(0.9, 8, 2, 8, 0.8, De=10.0, walls3=True).replace(precision="f64", check_every=20)
     init = K.perturbed_start(case, seed=4, amp=0.05, U_nom=0.05)
