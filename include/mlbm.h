@@ -59,12 +59,15 @@ typedef enum {
     MLBM_F32_C64 = 4      /* stored in FP32, collided in FP64                     */
 } mlbm_precision;
 /* 16-bit storage: population q at a node of x1 row i is stored as
- * f/w_q - 1 - r[i][q], r being the row mean of f/w_q - 1 of the initial
- * state (fixed at creation, kept in checkpoints). Stores round
+ * f/w_q - 1 - r[i][q], r being the row mean of f/w_q - 1, taken from the
+ * initial state at creation and again from the current state every 10
+ * windows of check_every steps of the instance (right before it steps on
+ * from such a step count; kept in checkpoints). Stores round
  * stochastically, seeded from (instance, node, step, q), so increments
  * below the storage resolution are kept on average; results are still
- * bitwise reproducible run to run. mlbm_set_populations and the initial
- * state round to nearest. */
+ * bitwise reproducible run to run, and do not depend on how the steps are
+ * grouped into calls, batches or graphs. mlbm_set_populations and the
+ * initial state round to nearest. */
 
 enum { MLBM_WALL_AXIS1 = 1, MLBM_WALL_AXIS3 = 4 };
 enum { MLBM_FORCING_IMPROVED = 0, MLBM_FORCING_OLD = 1 };

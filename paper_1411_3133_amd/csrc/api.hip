@@ -266,11 +266,47 @@ mlbm_status capture_window(Batch *B)
     return MLBM_OK;
 }
 
+// 16-bit storage: every REREF_WINDOWS windows of its own clock an instance
+// re-takes its reference row means from the current state, right before it
+// steps on (so the step counts at which it happens do not depend on how the
+// steps are grouped into calls, batches or graphs).
+constexpr int64_t REREF_WINDOWS = 10;
+
+int parity_of(const Instance &I) { return (int)(I.t & 1); }
+
+// true when an active instance reaches a re-reference step strictly inside
+// the next m steps (a graph window must not straddle one)
+bool reref_within(const Batch *B, int64_t m)
+{
+    if (!uses_ref(B->st)) return false;
+    const int64_t every = REREF_WINDOWS * B->K;
+    for (const auto &I : B->inst) {
+        if (!I.active) continue;
+        const int64_t to = (every - I.t % every) % every;
+        if (to > 0 && to < m) return true;
+    }
+    return false;
+}
+
+mlbm_status reref_due(Batch *B)
+{
+    if (!uses_ref(B->st)) return MLBM_OK;
+    const int64_t every = REREF_WINDOWS * B->K;
+    for (size_t i = 0; i < B->inst.size(); ++i) {
+        Instance &I = B->inst[i];
+        if (!I.active || I.t == 0 || I.t % every != 0) continue;
+        HIP_TRY(launch_reref(B->d_insts + i, I.hd, B->st, parity_of(I), const_cast<float *>(I.hd.ref), B->stream));
+    }
+    return MLBM_OK;
+}
+
 mlbm_status advance(Batch *B, int64_t n)
 {
     while (n > 0) {
+        mlbm_status rs = reref_due(B);
+        if (rs != MLBM_OK) return rs;
         const int64_t into = B->t % B->K;
-        if (into == 0 && n >= B->K && B->use_graph && B->ntiles > 0) {
+        if (into == 0 && n >= B->K && B->use_graph && B->ntiles > 0 && !reref_within(B, B->K)) {
             if (!B->graph_valid) {
                 mlbm_status s = capture_window(B);
                 if (s != MLBM_OK) return s;
@@ -296,8 +332,6 @@ mlbm_status read_ws(Batch *B, std::vector<WindowState> &ws)
     HIP_TRY(hipStreamSynchronize(B->stream));
     return MLBM_OK;
 }
-
-int parity_of(const Instance &I) { return (int)(I.t & 1); }
 
 GeoEntry *find_or_make_geo(Batch *B, const mlbm_desc &d, int &key, mlbm_status &st)
 {

@@ -31,6 +31,10 @@ hipError_t launch_ref(const InstDesc *d_desc, const InstDesc &h_desc, const doub
                       hipStream_t s);
 hipError_t launch_init(const InstDesc *d_desc, const InstDesc &h_desc, int st, const double *init_u,
                        int parity, hipStream_t s);
+// 16-bit storage: re-take the row means r from the current state (buffer
+// `parity`) and re-encode the stored values against them, in place
+hipError_t launch_reref(const InstDesc *d_desc, const InstDesc &h_desc, int st, int parity, float *ref,
+                        hipStream_t s);
 
 // residual / flag reduction over the partial sums of each instance's tiles
 hipError_t launch_reduce(const double *partials, const int *part_begin, const int *part_count,

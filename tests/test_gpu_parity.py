@@ -335,20 +335,22 @@ def test_instability_flag_from_planted_nan():
 def test_batch_graph_and_eager_are_bitwise_equal_to_single(prec):
     """Batched, graph-replayed and eager runs of the same instances agree bit
     for bit, also for 16-bit storage (its stochastic rounding is keyed by the
-    instance description, node and step, not by the batch position)."""
+    instance description, node and step, not by the batch position). 1130
+    steps cross two re-references of the 16-bit reference means (every 10
+    windows of 50 steps)."""
     # De up to 12 keeps the lattice Mach number below 0.4 on this small grid
     cases = [K.cylinder_case(0.95, 16, 4, 24, 0.7, De=De, walls3=True).replace(precision=prec, check_every=50)
              for De in (6.0, 9.0, 12.0)]
     inits = [K.perturbed_start(c, seed=7, amp=1e-2) for c in cases]
     b = mlbm.Batch(cases, inits)
-    b.step(130)
+    b.step(1130)
     single = mlbm.Sim(cases[1], init_u=inits[1])
-    single.step(130)
+    single.step(1130)
     assert np.array_equal(b[1].get_f(), single.get_f())
     e = mlbm.Batch(cases, inits)
     e.use_graph(False)
     e.set_launch(64, 0)
-    e.step(130)
+    e.step(1130)
     for i in range(3):
         assert np.all(np.isfinite(b[i].get_f()))
         assert np.array_equal(b[i].get_f(), e[i].get_f())
@@ -373,16 +375,43 @@ def test_persistent_grid_and_autotune_keep_results(prec):
         assert np.array_equal(a[i].get_f(), b[i].get_f())
 
 
+@pytest.mark.parametrize("prec,mant", [("f16", 10), ("bf16", 7)])
+def test_rereference_keeps_the_state(prec, mant):
+    """16-bit storage re-takes its reference row means every 10 windows,
+    right before the step from such a step count. The step after it matches
+    one step of the same state without it (mlbm_step_nodes, which does not
+    re-reference) on every node, within the storage rounding: the two paths
+    differ by three stochastic roundings (the re-reference and each path's
+    store), each below one unit in the last place of the largest stored
+    magnitude |f/w - 1 - r| under the old or the new row means."""
+    case = K.cylinder_case(0.95, 16, 4, 24, 0.7, De=12.0, walls3=True).replace(precision=prec, check_every=20)
+    g = mlbm.Sim(case, init_u=K.perturbed_start(case, seed=3, amp=1e-2))
+    _, w, _, _ = O.lattice()
+    shape = (41, case.n1, case.n2 * case.n3)
+    d0 = g.get_f().reshape(shape) / w[:, None, None] - 1.0
+    g.step(200)
+    d = g.get_f().reshape(shape) / w[:, None, None] - 1.0
+    big = max(np.abs(d - d0.mean(axis=2, keepdims=True)).max(), np.abs(d - d.mean(axis=2, keepdims=True)).max())
+    ulp = 2.0 ** (np.floor(np.log2(big)) - mant)
+    nodes = np.arange(case.N)
+    ref = g.step_nodes(nodes)
+    g.step(1)
+    got = g.get_f().reshape(41, -1).T
+    err = (np.abs(got - ref) / w[None, :]).max()
+    print(f"{prec}: step after re-referencing vs without, max |df|/w = {err:.3e} ({err / ulp:.2f} ulp)")
+    assert err < 4 * ulp
+
+
 def test_checkpoint_resume_is_bitwise(tmp_path):
     case = K.cylinder_case(0.9, 8, 4, 8, 0.8, De=10.0, walls3=True).replace(precision="f16", check_every=20)
     init = K.perturbed_start(case, seed=9, amp=0.05, U_nom=0.05)
     a = mlbm.Sim(case, init_u=init)
-    a.step(70)
+    a.step(200)                 # saved exactly at a re-reference step (every 10 windows of 20)
     path = str(tmp_path / "ck.bin")
     a.save(path)
-    a.step(50)
+    a.step(250)
     b = mlbm.Sim.load_checkpoint(path, case)
-    assert b.t == 70
-    b.step(50)
+    assert b.t == 200
+    b.step(250)
     assert np.array_equal(a.get_f(), b.get_f())
     assert a.residual() == b.residual()
