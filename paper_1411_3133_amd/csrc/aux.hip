@@ -190,7 +190,7 @@ hipError_t launch_ref(const InstDesc *d_desc, const InstDesc &h, const double *i
 // re-encoded against them. Against the initial means the stored magnitudes
 // |d - r| grow as the flow develops and its density drifts (a drift of the
 // mean density shifts every f/w - 1 alike), and the rounding noise grows
-// with them. One workgroup per x1 row; per population a fixed-order block
+// with them. One workgroup per (x1 row, population): a fixed-order block
 // reduction of the decoded values, then the re-encode in place (each value
 // is read and written by the same thread) with stochastic rounding keyed
 // apart from the steps' own.
@@ -199,39 +199,34 @@ __global__ void reref_kernel(const InstDesc *dd, int parity, float *ref)
 {
     using T = typename Codec<ST>::T;
     const InstDesc &d = *dd;
-    const int x1 = blockIdx.x;
+    const int x1 = blockIdx.x, q = blockIdx.y;
     __shared__ double part[256];
-    T *row = (T *)d.f[parity] + (size_t)x1 * Q * d.P;
-    const uint32_t ctr = d.ctr[parity];
-    const uint32_t key = mix32(d.salt ^ 0x2545F491u);
-    for (int q = 0; q < Q; ++q) {
-        const float r_old = ref[x1 * Q + q];
-        T *plane = row + (size_t)q * d.P;
-        double acc = 0.0;
-        for (int col = threadIdx.x; col < d.P; col += blockDim.x) acc += (double)Codec<ST>::decode(plane[col], r_old);
-        part[threadIdx.x] = acc;
+    T *plane = (T *)d.f[parity] + ((size_t)x1 * Q + q) * d.P;
+    const float r_old = ref[x1 * Q + q];
+    double acc = 0.0;
+    for (int col = threadIdx.x; col < d.P; col += blockDim.x) acc += (double)Codec<ST>::decode(plane[col], r_old);
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
         __syncthreads();
-        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-            __syncthreads();
-        }
-        const float r_new = (float)(part[0] / d.P);
-        for (int col = threadIdx.x; col < d.P; col += blockDim.x) {
-            const uint32_t n = (uint32_t)(x1 * d.P + col);
-            const uint32_t bits = mix32(key + n * 0x9E3779B9u + ctr * 0x85EBCA77u + (uint32_t)q * 0xC2B2AE3Du);
-            plane[col] = Codec<ST>::encode_sr(Codec<ST>::decode(plane[col], r_old), r_new, bits);
-        }
-        __syncthreads();   // every thread has read part[0] and r_old
-        if (threadIdx.x == 0) ref[x1 * Q + q] = r_new;
     }
+    const float r_new = (float)(part[0] / d.P);
+    const uint32_t key = mix32(d.salt ^ 0x2545F491u) + d.ctr[parity] * 0x85EBCA77u + (uint32_t)q * 0xC2B2AE3Du;
+    for (int col = threadIdx.x; col < d.P; col += blockDim.x) {
+        const uint32_t bits = mix32(key + (uint32_t)(x1 * d.P + col) * 0x9E3779B9u);
+        plane[col] = Codec<ST>::encode_sr(Codec<ST>::decode(plane[col], r_old), r_new, bits);
+    }
+    if (threadIdx.x == 0) ref[x1 * Q + q] = r_new;   // this workgroup is its only reader
 }
 
 hipError_t launch_reref(const InstDesc *d_desc, const InstDesc &h, int st, int parity, float *ref, hipStream_t s)
 {
+    const dim3 grid(h.n1, Q), block(256);
     if (st == ST_F16)
-        hipLaunchKernelGGL(reref_kernel<ST_F16>, dim3(h.n1), dim3(256), 0, s, d_desc, parity, ref);
+        hipLaunchKernelGGL(reref_kernel<ST_F16>, grid, block, 0, s, d_desc, parity, ref);
     else if (st == ST_BF16)
-        hipLaunchKernelGGL(reref_kernel<ST_BF16>, dim3(h.n1), dim3(256), 0, s, d_desc, parity, ref);
+        hipLaunchKernelGGL(reref_kernel<ST_BF16>, grid, block, 0, s, d_desc, parity, ref);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
