@@ -122,7 +122,7 @@ template <int PAT, class C, class R, bool SCALED = false>
 __host__ __device__ __forceinline__ void collide(R (&g)[Q], const NodeGeo<PAT, C> &G, C omega, C kappa,
                                                  C &rho_out, C (&u_out)[3])
 {
-    // register value = ws(q) * (f - w) / w: ws is the weight for scaled
+    // f - w = ws(q) * (register value): ws is the weight for scaled
     // registers, else 1
     constexpr auto ws = [](int q) constexpr { return SCALED ? C(wq(q)) : C(1); };
     constexpr C cs2 = (C)CS2;
