@@ -63,6 +63,43 @@ def test_window_residual_of_a_decaying_mode():
     assert abs(R / (math.exp(lam * K_win) - 1.0) - 1.0) < 1e-6
 
 
+@pytest.mark.parametrize("eta,n1,tau", [(0.9, 16, 0.8), (0.8, 16, 0.6), (0.9, 32, 0.8)])
+def test_rest_state_of_the_cylinder(eta, n1, tau):
+    """A cylinder channel without force, started at rest, stays at rest up to
+    small spurious currents, and its mass decays at the rate the velocity
+    reading implies. In hydrostatic balance the true velocity vanishes while
+    the covariant pressure source is S^r = -rho' c_s^2 / r; the collision
+    reads u = sum c f / rho' without the half-force shift, so it sees
+    u^r = -S^r / (2 rho') = c_s^2 / (2 r), and the forcing's mass source
+    -2 rho' u^i Gamma^j_ij (Gamma^theta_theta r = 1/r) removes
+    rho' c_s^2 / r^2 per step, r in lattice units. tau does not enter. This
+    pins the Christoffel and forcing normalisation together with the
+    velocity reading (a factor or sign error in any of them changes the
+    rate or its sign)."""
+    case = K.cylinder_case(eta, n1, 4, 8, tau, De=None).replace(precision="f64")
+    S = O.Sim(case)
+    S.step(300)
+    f0 = S.get_f()
+    m0 = f0.sum()
+    S.step(1000)
+    m1 = S.get_f().sum()
+    rate = math.log(m0 / m1) / 1000
+    _, _, cs2 = O.lattice()[:3]
+    dr = (1.0 / eta - 1.0) / n1                          # r_i = 1
+    r = (1.0 + (np.arange(n1) + 0.5) * dr) / dr          # node radius in lattice units
+    wts = f0.sum(axis=0).reshape(n1, -1).sum(axis=1)     # rho' per row
+    pred = float((cs2 / r ** 2 * wts).sum() / wts.sum())
+    _, u = S.moments()[:2]
+    ur = u[0].reshape(n1, -1) / (cs2 / (2.0 * r))[:, None]
+    print(f"eta {eta} n1 {n1} tau {tau}: drain {rate:.4e} per step, predicted {pred:.4e}; "
+          f"u^r / (c_s^2 / 2r) in [{ur.min():.3f}, {ur.max():.3f}]")
+    assert abs(rate / pred - 1.0) < 0.03
+    # the only velocity the collision sees is the radial offset of the
+    # reading (the slow drain adds a weak flow, hence the loose band)
+    assert np.all(np.abs(ur - 1.0) < 0.2)
+    assert np.abs(u[1:]).max() < 1e-12
+
+
 def _steady(case, tol=1e-10, max_steps=200000, init=None):
     S = O.Sim(case, init_u=K.poiseuille_field(case) if init is None else init)
     R, steps, bad = S.run_until(tol, 100, max_steps)
