@@ -49,8 +49,9 @@
  *   - flow: uniform flow is a fixed point, a shear wave decays with
  *     nu = cs2 (tau - 1/2), plane Poiseuille converges at second order, the
  *     curved profile tends to its closed form, the mass budget closes each
- *     step, the window residual of a single decaying mode equals
- *     exp(lambda K) - 1;
+ *     step, a cylinder at rest drains mass at rho' c_s^2 / r^2 per step
+ *     (hydrostatic balance under the velocity reading), the window residual
+ *     of a single decaying mode equals exp(lambda K) - 1;
  *   - observables: vorticity and mean velocity of closed-form fields.
  * Every function here has at least one such pin.
  *
