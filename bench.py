@@ -140,7 +140,7 @@ def uneven_batch_leg(precision, steps=1000, warmup=200):
     cases = K.uneven_ellipsoid_batch(precision=precision)
     inits = [K.perturbed_start(c, seed=3133 + i, amp=1e-4) for i, c in enumerate(cases)]
     b = mlbm.Batch(cases, inits, stream=torch.cuda.current_stream())
-    block, grid = b.autotune(steps=10)
+    block, grid = b.autotune(steps=50)
     b.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -173,7 +173,7 @@ def beyond_cache_leg(precision, steps=500, warmup=100, block=0, grid=0):
     if block:
         b.set_launch(block, grid)
     else:
-        block, grid = b.autotune(steps=10)
+        block, grid = b.autotune(steps=50)
     b.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -289,7 +289,7 @@ def main():
         block, grid = args.block, args.grid
         batch.set_launch(block, grid)
     elif not args.no_autotune:
-        block, grid = batch.autotune(steps=20)
+        block, grid = batch.autotune(steps=100)
     batch.step(args.warmup)
     torch.cuda.synchronize()
     # timed region
