@@ -229,6 +229,10 @@ def critical_dean_leg(tol=1e-7):
         "workload": f"{len(pairs)} curvature pairs of the batched sweep (R2/d >= 18), ellipsoid slabs 32x4xn3, "
                     f"De grid 20..80 then bisection to 1 % brackets, FP64, residual {tol:g}",
         "onsets_plain_warm": onsets,
+        # onset read off the <omega>(measured De) curve of converged runs,
+        # the paper's way of reading it, beside the 2-cell onsets above
+        "omega_knees_plain_warm": {name: [None if res[w]["knees"][name] is None else round(res[w]["knees"][name], 3)
+                                          for w in (False, True)] for name in res[False]["knees"]},
         "max_rel_diff": round(max(diffs), 5) if diffs else None,
         "within_1pct": f"{sum(d <= 0.01 for d in diffs)}/{len(diffs)}",
         "seconds_plain": res[False]["seconds"], "seconds_warm": res[True]["seconds"],

@@ -22,16 +22,44 @@ from .mlbm import Net
 
 
 def _run(cases, inits_plain, tol, max_steps, net=None, fallback_after=None, log=None):
-    """Fields, steps, status and measured De of a batch of cases."""
+    """Fields, steps, status and observables (<omega>, <v_theta>, measured De)
+    of a batch of cases."""
     if net is None:
         b, steps, status, secs = W.run_to_steady(cases, inits_plain, tol, max_steps, log=log)
         fields = [b[i].moments() for i in range(len(cases))]
-        De = np.array([b[i].vortex_intensity()[2] for i in range(len(cases))])
+        obs = [b[i].vortex_intensity() for i in range(len(cases))]
         b.close()
-        return fields, steps, status, De, secs
+        return fields, steps, status, obs, secs
     fields, steps, status, secs, _, _, _, obs = W.warm_start_run(net, cases, inits_plain, tol, max_steps,
                                                                  fallback_after, log)
-    return fields, steps, status, np.array([o[2] for o in obs]), secs
+    return fields, steps, status, obs, secs
+
+
+def knee(De: Sequence[float], omega: Sequence[float]):
+    """Onset read off a vorticity curve, the way Sec. III and IV read the
+    critical Dean number: the best two-segment least-squares fit of
+    <omega>(De), a lower segment below onset and a rising one above it (at
+    least two points each), and the intersection of the two lines. None when
+    no split has an upper segment steeper than the lower one (by more than
+    rounding: a slope change worth 1e-6 of the largest |<omega>| over the
+    De range)."""
+    x = np.asarray(De, dtype=float)
+    y = np.asarray(omega, dtype=float)
+    order = np.argsort(x)
+    x, y = x[order], y[order]
+    if len(x) < 4:
+        return None
+    min_rise = 1e-6 * float(np.abs(y).max()) / max(float(x[-1] - x[0]), 1e-300)
+    best = None
+    for s in range(2, len(x) - 1):
+        lo = np.polyfit(x[:s], y[:s], 1)
+        hi = np.polyfit(x[s:], y[s:], 1)
+        if hi[0] - lo[0] <= min_rise:
+            continue
+        res = float(np.sum((np.polyval(lo, x[:s]) - y[:s]) ** 2) + np.sum((np.polyval(hi, x[s:]) - y[s:]) ** 2))
+        if best is None or res < best[0]:
+            best = (res, float((lo[1] - hi[1]) / (hi[0] - lo[0])))
+    return None if best is None else best[1]
 
 
 def critical_dean(pairs: Sequence[Tuple[str, Callable[[float], K.Case]]], De_grid: Sequence[float],
@@ -40,18 +68,20 @@ def critical_dean(pairs: Sequence[Tuple[str, Callable[[float], K.Case]]], De_gri
                   train_steps=((8000, 2e-3), (6000, 5e-4), (3000, 1e-4)), fallback_after: int = 60000,
                   log=None) -> Dict:
     """Bracket the onset De of k cells for every pair; returns brackets of
-    nominal and measured De per (pair, k), the cell counts seen, and wall
-    time and instance-steps per round."""
+    nominal and measured De per (pair, k), the onset read off each pair's
+    <omega>(measured De) curve of converged runs (`knee`), the cell counts
+    and <omega> seen, and wall time and instance-steps per round."""
     t_all = time.perf_counter()
-    seen: Dict[Tuple[str, float], Tuple[int, float, int]] = {}   # (pair, De_nom) -> (cells, De_meas, status)
+    # (pair, De_nom) -> (cells, De_meas, status, <omega>)
+    seen: Dict[Tuple[str, float], Tuple[int, float, int, float]] = {}
     rounds = []
 
     def run_round(items, net=None):
         cases = [make(De) for (_, make, De) in items]
         plain = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
-        fields, steps, status, De_meas, secs = _run(cases, plain, tol, max_steps, net, fallback_after, log)
-        for (name, _, De), c, (_, u), st, dm in zip(items, cases, fields, status, De_meas):
-            seen[(name, De)] = (W.cell_count(c, u), float(dm), int(st))
+        fields, steps, status, obs, secs = _run(cases, plain, tol, max_steps, net, fallback_after, log)
+        for (name, _, De), c, (_, u), st, ob in zip(items, cases, fields, status, obs):
+            seen[(name, De)] = (W.cell_count(c, u), float(ob[2]), int(st), float(ob[0]))
         rounds.append({"instances": len(items), "seconds": round(secs, 3), "instance_steps": int(np.sum(steps)),
                        "converged": int(np.sum(status == 0)), "unstable": int(np.sum(status == 2))})
         return cases, fields, status
@@ -106,6 +136,11 @@ def critical_dean(pairs: Sequence[Tuple[str, Callable[[float], K.Case]]], De_gri
                 "status_at_ends": [seen[(name, lo)][2] if lo is not None else None,
                                    seen[(name, hi)][2] if hi is not None else None],
             }
-    return {"onsets": out, "rounds": rounds, "train_seconds": round(t_train, 2),
+    knees = {}
+    for name, _ in pairs:
+        pts = [(v[1], v[3]) for (n, _), v in seen.items() if n == name and v[2] == 0]
+        knees[name] = knee([p[0] for p in pts], [p[1] for p in pts]) if len(pts) >= 4 else None
+    return {"onsets": out, "knees": knees, "rounds": rounds, "train_seconds": round(t_train, 2),
             "seconds": round(time.perf_counter() - t_all, 2),
-            "cells": {f"{n}@{De:g}": v[0] for (n, De), v in sorted(seen.items())}}
+            "cells": {f"{n}@{De:g}": v[0] for (n, De), v in sorted(seen.items())},
+            "omega": {f"{n}@{De:g}": v[3] for (n, De), v in sorted(seen.items())}}

@@ -27,14 +27,16 @@ def fake_runs(monkeypatch):
 
     def fake_run(cases, inits, tol, max_steps, net=None, fallback_after=None, log=None):
         calls.append(len(cases))
-        fields, De = [], []
+        fields, obs = [], []
         for c in cases:
             th = THRESH[c.label]
             cells = max([0] + [k for k, t in th.items() if c.target_De >= t])
             fields.append((None, _field(c, cells)))
-            De.append(0.97 * c.target_De)
+            De = 0.97 * c.target_De
+            omega = 0.01 * max(0.0, De - 0.97 * th[2])     # vorticity rises linearly past the 2-cell onset
+            obs.append((omega, 1.0, De))
         n = len(cases)
-        return fields, np.full(n, 1000), np.zeros(n, np.int32), np.array(De), 0.01
+        return fields, np.full(n, 1000), np.zeros(n, np.int32), obs, 0.01
 
     monkeypatch.setattr(sweep, "_run", fake_run)
     return calls
@@ -60,6 +62,9 @@ def test_brackets_close_on_thresholds(fake_runs):
     assert fake_runs[0] == 2 * len(grid)
     assert all(n <= 2 * 3 for n in fake_runs[1:])
     assert len(r["rounds"]) == len(fake_runs)
+    # the vorticity knee sits on the 2-cell onset (measured De)
+    for name in ("A", "B"):
+        assert r["knees"][name] == pytest.approx(0.97 * THRESH[name][2], rel=1e-9)
 
 
 def test_onset_below_grid_is_open(fake_runs):
@@ -68,3 +73,20 @@ def test_onset_below_grid_is_open(fake_runs):
     lo, hi = r["onsets"]["A/k2"]["De_nominal"]
     assert lo is None and hi == 40.0       # already 2 cells at the lowest De: no bracket
     assert len(fake_runs) == 1
+
+
+def test_knee_of_a_piecewise_linear_curve():
+    x = np.arange(20.0, 85.0, 5.0)
+    y = np.where(x < 41.3, 0.002, 0.002 + 0.03 * (x - 41.3))
+    assert sweep.knee(x, y) == pytest.approx(41.3, rel=1e-9)
+    # order of the samples does not matter
+    p = np.random.default_rng(1).permutation(len(x))
+    assert sweep.knee(x[p], y[p]) == pytest.approx(41.3, rel=1e-9)
+
+
+def test_knee_is_stable_under_small_noise_and_absent_without_a_rise():
+    x = np.arange(20.0, 85.0, 2.5)
+    y = np.maximum(0.0, x - 47.0) * 0.02 + 1e-4 * np.random.default_rng(2).normal(size=len(x))
+    assert abs(sweep.knee(x, y) - 47.0) < 0.5
+    assert sweep.knee(x, np.full(len(x), 0.3)) is None          # flat: no rising segment
+    assert sweep.knee(x, 1.0 - 0.01 * x) is None                # falling throughout
