@@ -28,11 +28,23 @@ HBM_PEAK_GBS = 8000.0
 BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "f32c64": 4}
 
 
-def kernel_source_digest():
+def _code_only(text):
+    """Source text without comments and blank-line or trailing-space
+    differences (a comment edit does not change the kernel)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
+def kernel_source_digest(read=None):
+    """Digest of the step kernel's code (its sources without comments)."""
+    if read is None:
+        def read(fn):
+            with open(os.path.join(ROOT, "paper_1411_3133_amd", "csrc", fn)) as f:
+                return f.read()
     h = hashlib.sha256()
     for fn in ("core.hpp", "step.hip", "common.hpp", "lattice.hpp"):
-        with open(os.path.join(ROOT, "paper_1411_3133_amd", "csrc", fn), "rb") as f:
-            h.update(f.read())
+        h.update(_code_only(read(fn)).encode())
     return h.hexdigest()[:16]
 
 

@@ -2,7 +2,8 @@
 //
 // HBM layout of one instance:
 //   populations  two buffers (pull: read one, write the other), each
-//                [41][n1][n2][n3] of the storage type, x3 fastest.  Stored
+//                [n1][41][n2][n3] of the storage type (the 41 planes of an
+//                x1 row together), x3 fastest.  Stored
 //                values are offsets from the lattice weights: g = f - w_q
 //                for FP64/FP32, d = f / w_q - 1 - r for FP16/BF16 (r: the
 //                row's reference offset of the population).
