@@ -140,7 +140,7 @@ def time_to_steady(n_train, n_test, tol=1e-6, cap=150000):
     }
 
 
-def uneven_batch_leg(precision, steps=1000, warmup=200):
+def uneven_batch_leg(precision, steps=1000, warmup=200, block=0, grid=0):
     """Throughput of the persistent kernel on the uneven ellipsoid batch: 64
     double-curved instances of 8 curvature pairs (N_r 45..96, N_phi 64..240,
     2.9 M nodes), one launch per step over all of them, autotuned launch,
@@ -152,7 +152,10 @@ def uneven_batch_leg(precision, steps=1000, warmup=200):
     cases = K.uneven_ellipsoid_batch(precision=precision)
     inits = [K.perturbed_start(c, seed=3133 + i, amp=1e-4) for i, c in enumerate(cases)]
     b = mlbm.Batch(cases, inits, stream=torch.cuda.current_stream())
-    block, grid = b.autotune(steps=50)
+    if block:
+        b.set_launch(block, grid)
+    else:
+        block, grid = b.autotune(steps=50)
     b.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -362,7 +365,7 @@ def main():
     }
     batch.close()
     if args.uneven:
-        line["uneven_batch"] = uneven_batch_leg(args.precision)
+        line["uneven_batch"] = uneven_batch_leg(args.precision, block=args.block, grid=args.grid)
     if args.beyond_cache:
         line["beyond_cache"] = beyond_cache_leg(args.precision, block=args.block, grid=args.grid)
     if args.steady > 0:
