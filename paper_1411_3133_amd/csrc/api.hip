@@ -203,13 +203,20 @@ mlbm_status build_tiles(Batch *B)
             for (int c = 0; c < I.hd.tpr; ++c) tiles.push_back(Tile{(int)i, x1, c, (int)tiles.size()});
         pc[i] = (int)tiles.size() - pb[i];
     }
-    B->ntiles = (int)tiles.size();
-    if ((int)tiles.size() > B->tiles_cap) {
+    const int ntiles = (int)tiles.size();
+    // The captured window and the device lists are replaced together: wait
+    // for every launch that reads the old ones, drop the window, and launch
+    // nothing (ntiles = 0) unless the new lists are all in place.
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    destroy_graph(B);
+    B->ntiles = 0;
+    if (ntiles > B->tiles_cap) {
         if (B->d_tiles) HIP_TRY(hipFree(B->d_tiles));
         if (B->d_partials) HIP_TRY(hipFree(B->d_partials));
         B->d_tiles = nullptr;
         B->d_partials = nullptr;
-        const int cap = std::max<int>(1, (int)tiles.size());
+        B->tiles_cap = 0;
+        const int cap = std::max<int>(1, ntiles);
         HIP_TRY(hipMalloc(&B->d_tiles, sizeof(Tile) * cap));
         HIP_TRY(hipMalloc(&B->d_partials, sizeof(double) * 3 * cap));
         B->tiles_cap = cap;
@@ -219,11 +226,11 @@ mlbm_status build_tiles(Batch *B)
     HIP_TRY(hipMemcpyAsync(B->d_insts, hds.data(), sizeof(InstDesc) * hds.size(), hipMemcpyHostToDevice, B->stream));
     if (!tiles.empty())
         HIP_TRY(hipMemcpyAsync(B->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, B->stream));
-    HIP_TRY(hipMemcpyAsync(B->d_ntiles, &B->ntiles, sizeof(int), hipMemcpyHostToDevice, B->stream));
+    HIP_TRY(hipMemcpyAsync(B->d_ntiles, &ntiles, sizeof(int), hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipMemcpyAsync(B->d_pb, pb.data(), sizeof(int) * pb.size(), hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipMemcpyAsync(B->d_pc, pc.data(), sizeof(int) * pc.size(), hipMemcpyHostToDevice, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));   // host vectors go out of scope
-    destroy_graph(B);
+    B->ntiles = ntiles;
     return MLBM_OK;
 }
 
@@ -876,11 +883,19 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
         Instance &I = B->inst[i];
         if (!I.active) continue;
         const size_t bytes = sb * Q * (size_t)I.hd.N;
-        HIP_TRY(hipMalloc(&backup[i], bytes));
-        HIP_TRY(hipMemcpyAsync(backup[i], I.hd.f[parity_of(I)], bytes, hipMemcpyDeviceToDevice, B->stream));
-        if (I.hd.ctr)
-            HIP_TRY(hipMemcpyAsync(ctr_backup.data() + 2 * i, I.hd.ctr, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                   B->stream));
+        hipError_t e = hipMalloc(&backup[i], bytes);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(backup[i], I.hd.f[parity_of(I)], bytes, hipMemcpyDeviceToDevice, B->stream);
+        if (e == hipSuccess && I.hd.ctr)
+            e = hipMemcpyAsync(ctr_backup.data() + 2 * i, I.hd.ctr, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               B->stream);
+        if (e != hipSuccess) {                      // nothing stepped yet: drop the backups taken so far
+            (void)hipStreamSynchronize(B->stream);
+            for (void *p : backup)
+                if (p) (void)hipFree(p);
+            return fail(e == hipErrorOutOfMemory ? MLBM_E_OOM : MLBM_E_HIP,
+                        std::string("autotune backup: ") + hipGetErrorString(e));
+        }
     }
     const int blocks[4] = {64, 128, 256, 512};
     const int grids[4] = {0, 2 * B->num_cu, 4 * B->num_cu, 8 * B->num_cu};
