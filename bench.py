@@ -267,9 +267,9 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="force the workgroup size (skips the autotuner)")
     ap.add_argument("--grid", type=int, default=0, help="persistent grid with --block (0: one workgroup per tile)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--steady", type=int, default=16,
+    ap.add_argument("--steady", type=int, default=64,
                     help="unseen cases in the time-to-steady leg (0 skips it)")
-    ap.add_argument("--steady-train", type=int, default=64, help="training fields for the warm start")
+    ap.add_argument("--steady-train", type=int, default=500, help="training fields for the warm start")
     ap.add_argument("--critical", type=int, default=1, help="run the critical-De leg (0 skips it)")
     ap.add_argument("--uneven", type=int, default=1, help="time the uneven ellipsoid batch (0 skips it)")
     ap.add_argument("--beyond-cache", type=int, default=1,
