@@ -270,11 +270,12 @@ def test_ellipsoid_96x192_16bit_step_kernel_at_full_size(prec, tol):
     g.close()
 
 
-@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f16", 2.0 ** -8)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 1e-5), ("f16", 2.0 ** -8), ("bf16", 2.0 ** -5)])
 def test_beyond_cache_step_kernel_at_full_size(prec, tol):
     """The instance bench.py's beyond-cache leg times (ellipsoid 96 x 192
-    cross-section, 192 slabs in FP32 and 384 in FP16: 3.5 M and 7.1 M nodes,
-    the largest population offsets the kernels address), in the autotuned
+    cross-section, 192 slabs for 8- and 4-byte storage, 384 for 2-byte: 3.5 M
+    and 7.1 M nodes; FP64 has the largest byte offsets the kernels address,
+    1.2 GB into a buffer), in the autotuned
     launch: after 100 steps, one more step; sampled stored populations
     (walls, the last slab and interior) match the FP64 oracle applied to the
     decoded pre-step state."""
