@@ -47,6 +47,23 @@ mlbm_status nfail(mlbm_status s, const std::string &m)
                          std::string(#expr) + ": " + hipGetErrorString(e_));                            \
     } while (0)
 
+// Device memory owned by one call: freed on every return path, once the
+// stream is done with it.
+struct CallBuf {
+    hipStream_t s;
+    void *p = nullptr;
+    explicit CallBuf(hipStream_t st) : s(st) {}
+    ~CallBuf()
+    {
+        if (p) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(p);
+        }
+    }
+    CallBuf(const CallBuf &) = delete;
+    CallBuf &operator=(const CallBuf &) = delete;
+};
+
 struct Shape {
     int H, depth;
     long np;
@@ -361,7 +378,12 @@ hipError_t dispatch_H(int H, F &&f)
 mlbm_status ensure_batch(mlbm_net_s *N, int64_t n)
 {
     if (n <= N->bcap) return MLBM_OK;
+    (void)hipStreamSynchronize(N->stream);
     (void)hipFree(N->Y); (void)hipFree(N->hid); (void)hipFree(N->dl); (void)hipFree(N->part); (void)hipFree(N->sel); (void)hipFree(N->lossp);
+    N->Y = N->hid = N->dl = N->part = nullptr;   // nothing dangles if an allocation below fails
+    N->sel = nullptr;
+    N->lossp = nullptr;
+    N->bcap = 0;
     const int H = N->sh.H, D = N->sh.depth;
     const int64_t nch = (n + CHUNK - 1) / CHUNK;
     NET_TRY(hipMalloc(&N->Y, sizeof(float) * NOUT * n));
@@ -478,8 +500,9 @@ mlbm_status mlbm_net_forward(mlbm_net N, const float *x, int64_t n, float *y)
     if (!N || !x || !y || n <= 0) return nfail(MLBM_E_ARG, "null argument or n <= 0");
     mlbm_status st = ensure_batch(N, n);
     if (st != MLBM_OK) return st;
-    float *dx = nullptr;
-    NET_TRY(hipMalloc(&dx, sizeof(float) * NIN * n));
+    CallBuf bx(N->stream);
+    NET_TRY(hipMalloc(&bx.p, sizeof(float) * NIN * n));
+    float *dx = (float *)bx.p;
     NET_TRY(hipMemcpyAsync(dx, x, sizeof(float) * NIN * n, hipMemcpyHostToDevice, N->stream));
     const Shape sh = N->sh;
     const int64_t nch = (n + CHUNK - 1) / CHUNK;
@@ -491,7 +514,6 @@ mlbm_status mlbm_net_forward(mlbm_net N, const float *x, int64_t n, float *y)
     });
     if (e == hipSuccess) e = hipMemcpyAsync(y, N->Y, sizeof(float) * NOUT * n, hipMemcpyDeviceToHost, N->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(N->stream);
-    (void)hipFree(dx);
     NET_TRY(e);
     return MLBM_OK;
 }
@@ -499,9 +521,10 @@ mlbm_status mlbm_net_forward(mlbm_net N, const float *x, int64_t n, float *y)
 mlbm_status mlbm_net_gradient(mlbm_net N, const float *x, const float *t, int64_t n, double *loss, double *grad)
 {
     if (!N || !x || !t || n <= 0) return nfail(MLBM_E_ARG, "null argument or n <= 0");
-    float *dx = nullptr, *dt = nullptr;
-    NET_TRY(hipMalloc(&dx, sizeof(float) * NIN * n));
-    NET_TRY(hipMalloc(&dt, sizeof(float) * NOUT * n));
+    CallBuf bx(N->stream), bt(N->stream);
+    NET_TRY(hipMalloc(&bx.p, sizeof(float) * NIN * n));
+    NET_TRY(hipMalloc(&bt.p, sizeof(float) * NOUT * n));
+    float *dx = (float *)bx.p, *dt = (float *)bt.p;
     NET_TRY(hipMemcpyAsync(dx, x, sizeof(float) * NIN * n, hipMemcpyHostToDevice, N->stream));
     NET_TRY(hipMemcpyAsync(dt, t, sizeof(float) * NOUT * n, hipMemcpyHostToDevice, N->stream));
     mlbm_status st = run_gradient(N, dx, dt, n, n, 0, loss);
@@ -512,9 +535,6 @@ mlbm_status mlbm_net_gradient(mlbm_net N, const float *x, const float *t, int64_
         if (e != hipSuccess) st = nfail(MLBM_E_HIP, hipGetErrorString(e));
         for (long k = 0; k < N->sh.np; ++k) grad[k] = h[k];
     }
-    (void)hipStreamSynchronize(N->stream);
-    (void)hipFree(dx);
-    (void)hipFree(dt);
     return st;
 }
 
@@ -535,26 +555,27 @@ mlbm_status mlbm_net_dataset_add(mlbm_net N, const mlbm_desc *d, double De, doub
     const int64_t N3 = (int64_t)d->n1 * d->n2 * d->n3;
     if (N->M + P > N->cap) {
         const int64_t cap = std::max<int64_t>(2 * N->cap, N->M + P);
-        float *X = nullptr, *T = nullptr;
-        NET_TRY(hipMalloc(&X, sizeof(float) * NIN * cap));
-        NET_TRY(hipMalloc(&T, sizeof(float) * NOUT * cap));
+        CallBuf bX(N->stream), bT(N->stream);
+        NET_TRY(hipMalloc(&bX.p, sizeof(float) * NIN * cap));
+        NET_TRY(hipMalloc(&bT.p, sizeof(float) * NOUT * cap));
         if (N->M) {
-            NET_TRY(hipMemcpyAsync(X, N->X, sizeof(float) * NIN * N->M, hipMemcpyDeviceToDevice, N->stream));
-            NET_TRY(hipMemcpyAsync(T, N->T, sizeof(float) * NOUT * N->M, hipMemcpyDeviceToDevice, N->stream));
-            NET_TRY(hipStreamSynchronize(N->stream));
+            NET_TRY(hipMemcpyAsync(bX.p, N->X, sizeof(float) * NIN * N->M, hipMemcpyDeviceToDevice, N->stream));
+            NET_TRY(hipMemcpyAsync(bT.p, N->T, sizeof(float) * NOUT * N->M, hipMemcpyDeviceToDevice, N->stream));
         }
+        NET_TRY(hipStreamSynchronize(N->stream));
         (void)hipFree(N->X);
         (void)hipFree(N->T);
-        N->X = X;
-        N->T = T;
+        N->X = (float *)bX.p;              // the set takes the new buffers over
+        N->T = (float *)bT.p;
+        bX.p = bT.p = nullptr;
         N->cap = cap;
     }
     const double *du = u;
-    double *tmp = nullptr;
+    CallBuf btmp(N->stream);
     if (!on_device) {
-        NET_TRY(hipMalloc(&tmp, sizeof(double) * 3 * N3));
-        NET_TRY(hipMemcpyAsync(tmp, u, sizeof(double) * 3 * N3, hipMemcpyHostToDevice, N->stream));
-        du = tmp;
+        NET_TRY(hipMalloc(&btmp.p, sizeof(double) * 3 * N3));
+        NET_TRY(hipMemcpyAsync(btmp.p, u, sizeof(double) * 3 * N3, hipMemcpyHostToDevice, N->stream));
+        du = (const double *)btmp.p;
     }
     const CaseGeo c = case_geo(*d, De, R1_d, R2_d);
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, N->stream, c, N->X + NIN * N->M);
@@ -562,7 +583,6 @@ mlbm_status mlbm_net_dataset_add(mlbm_net N, const mlbm_desc *d, double De, doub
                        N->T + NOUT * N->M);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(N->stream);
-    if (tmp) (void)hipFree(tmp);
     NET_TRY(e);
     N->M += P;
     return MLBM_OK;
@@ -617,10 +637,11 @@ mlbm_status mlbm_warmstart_predict(mlbm_net N, const mlbm_desc *d, double De, do
     const int64_t N3 = (int64_t)d->n1 * d->n2 * d->n3;
     mlbm_status st = ensure_batch(N, P);
     if (st != MLBM_OK) return st;
-    float *X = nullptr;
-    double *du = nullptr;
-    NET_TRY(hipMalloc(&X, sizeof(float) * NIN * P));
-    if (!on_device) NET_TRY(hipMalloc(&du, sizeof(double) * 3 * N3));
+    CallBuf bX(N->stream), bu(N->stream);
+    NET_TRY(hipMalloc(&bX.p, sizeof(float) * NIN * P));
+    if (!on_device) NET_TRY(hipMalloc(&bu.p, sizeof(double) * 3 * N3));
+    float *X = (float *)bX.p;
+    double *du = (double *)bu.p;
     const CaseGeo c = case_geo(*d, De, R1_d, R2_d);
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, N->stream, c, X);
     const Shape sh = N->sh;
@@ -640,8 +661,6 @@ mlbm_status mlbm_warmstart_predict(mlbm_net N, const mlbm_desc *d, double De, do
     if (e == hipSuccess && !on_device)
         e = hipMemcpyAsync(u_out, du, sizeof(double) * 3 * N3, hipMemcpyDeviceToHost, N->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(N->stream);
-    (void)hipFree(X);
-    if (du) (void)hipFree(du);
     NET_TRY(e);
     return MLBM_OK;
 }
