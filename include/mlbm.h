@@ -169,7 +169,8 @@ int64_t mlbm_time(mlbm_handle h);
 mlbm_status mlbm_save(mlbm_handle h, const char *path);
 mlbm_status mlbm_load(const char *path, void *hip_stream, mlbm_handle *out);
 
-/* Free the handle and its device memory (NULL is ignored). */
+/* Free the handle and its device memory (NULL is ignored); for a batch
+ * view, only the view handle. */
 void mlbm_destroy(mlbm_handle h);
 
 /* Thread-local text of the last error. */
@@ -195,10 +196,11 @@ mlbm_status mlbm_batch_step(mlbm_batch b, int64_t n);
 mlbm_status mlbm_batch_run_until(mlbm_batch b, double tol, int64_t max_steps, int64_t *steps,
                                  double *residual, int32_t *status);
 
-/* Non-owning view of instance i, valid until the batch is destroyed; every
+/* Non-owning view of instance i, usable until the batch is destroyed; every
  * single-instance query above (moments, vortex_intensity, residual,
- * get/set_populations, step_nodes, time) accepts it.  mlbm_step and
- * mlbm_destroy on a view return E_STATE / do nothing. */
+ * get/set_populations, step_nodes, time) accepts it.  mlbm_step on a view
+ * returns E_STATE.  mlbm_destroy on a view frees the view handle only (the
+ * batch stays), before or after the batch is destroyed. */
 mlbm_status mlbm_batch_get(mlbm_batch b, int i, mlbm_handle *view);
 
 /* Launch shape: workgroup size (64, 128, 256, 512) and persistent grid

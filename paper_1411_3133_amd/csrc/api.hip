@@ -579,10 +579,8 @@ mlbm_status mlbm_init_geometry(const mlbm_desc *d, void *hip_stream, mlbm_handle
 void mlbm_destroy(mlbm_handle h)
 {
     if (!h) return;
-    if (h->owner) {
-        free_batch(h->b);
-        delete h;
-    }
+    if (h->owner) free_batch(h->b);   // a view frees only itself, never its batch
+    delete h;
 }
 
 void mlbm_batch_destroy(mlbm_batch b)

@@ -187,7 +187,8 @@ class Sim:
         self.N = case.N
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._owner:
+        # an owning handle frees its instance; a view frees only itself
+        if getattr(self, "_h", None) is not None:
             load().mlbm_destroy(self._h)
         self._h = None
 
@@ -287,6 +288,8 @@ class Batch:
         return self.views[i]
 
     def close(self):
+        for v in getattr(self, "views", []):
+            v.close()
         if getattr(self, "_h", None) is not None:
             load().mlbm_batch_destroy(self._h)
         self._h = None
