@@ -289,7 +289,7 @@ def main():
                           "copy_bytes_written_per_launch": a.numel() * 4}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
