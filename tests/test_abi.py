@@ -67,6 +67,9 @@ def test_kernel_streaming_fold_at_benchmark_sizes():
     dict(n1=0), dict(tau=0.5), dict(tau=0.3), dict(width=0.0), dict(walls=8),
     dict(n1=3), dict(check_every=3), dict(precision="f64", forcing_mode=2),
     dict(kind="ellipsoid", b=0.0), dict(kind="ellipsoid", n3=4000, b=1.0),
+    # largest sizes: a population buffer of 4 GiB or more, and a cross
+    # section past the division by n3 the kernels use (n2 n3 >= 2^20)
+    dict(n1=600, n2=600, n3=600), dict(n1=4, n2=1100, n3=1000, precision="f16"),
 ])
 def test_invalid_descriptions_are_rejected_before_any_device_work(bad):
     case = K.laminar_cylinder()
@@ -87,3 +90,11 @@ def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(mlbm, "_lib", None)
     with pytest.raises(ImportError):
         mlbm.load()
+
+
+def test_empty_batch_is_rejected_before_any_device_work():
+    import ctypes as C
+    d, _ = mlbm.make_desc(K.laminar_cylinder())
+    b = C.c_void_p()
+    assert mlbm.load().mlbm_batch_create(C.byref(d), 0, None, C.byref(b)) == mlbm.E_ARG
+    assert mlbm.load().mlbm_last_error()
