@@ -164,6 +164,28 @@ def test_reduced_precision_velocity_and_dean_error(ellipsoid_oracle, prec):
 # collision for f32; for the 16-bit formats stochastic rounding errs by less
 # than one unit in the last place, which for stored magnitudes below 4 is
 # 2^-8 (binary16) and 2^-5 (bfloat16).
+@pytest.mark.parametrize("prec,rtol", [("f64", 0.03), ("f32", 0.03)])
+def test_rest_state_drain_of_the_cylinder(prec, rtol):
+    """The kernel at rest (no force) in the cylinder: total mass decays at
+    rho' c_s^2 / r^2 per step (r in lattice units), the rate the velocity
+    reading implies (the same closed form pins the oracle)."""
+    eta, n1 = 0.9, 16
+    case = K.cylinder_case(eta, n1, 4, 8, 0.8, De=None).replace(precision=prec)
+    g = mlbm.Sim(case)
+    g.step(300)
+    f0 = g.get_f()
+    g.step(1000)
+    f1 = g.get_f()
+    rate = np.log(f0.sum() / f1.sum()) / 1000
+    _, _, cs2, _ = O.lattice()
+    dr = (1.0 / eta - 1.0) / n1
+    r = (1.0 + (np.arange(n1) + 0.5) * dr) / dr
+    wts = f0.reshape(41, n1, -1).sum(axis=(0, 2))
+    pred = float((cs2 / r ** 2 * wts).sum() / wts.sum())
+    print(f"{prec}: drain {rate:.4e} per step, predicted {pred:.4e}")
+    assert abs(rate / pred - 1.0) < rtol
+
+
 def test_cylinder_sweep_steady_states_fp32_against_fp64():
     """Curved-channel sweep instances (64 x 4 x 256, end walls, De 30..60)
     run to R <= 1e-6 from the seeded perturbed start, FP32 storage and
