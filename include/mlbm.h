@@ -151,7 +151,11 @@ mlbm_status mlbm_get_populations(mlbm_handle h, double *f);
 mlbm_status mlbm_set_populations(mlbm_handle h, const double *f);
 
 /* One step of the nodes listed, from the current state, without advancing:
- * out[k][41] = f* at node nodes[k] (host arrays).  Waits for the stream. */
+ * out[k][41] = f* at node nodes[k] (host arrays), rounded through the
+ * storage format as the step would store it.  With 16-bit storage at a
+ * re-referencing step count it uses the current reference, not the one the
+ * next step will re-take (the two differ by the storage rounding).  Waits
+ * for the stream. */
 mlbm_status mlbm_step_nodes(mlbm_handle h, const int64_t *nodes, int64_t count, double *out);
 
 /* Pull map of the streaming step with walls, evaluated on the host with the
