@@ -62,21 +62,31 @@ def measured_traffic(workload_tag, digest):
     return float(m_t.group(1))
 
 
-def cpu_baseline(case, init, budget_s=12.0):
-    """The FP64 oracle on one instance of the workload, timed on host cores."""
+def cpu_baseline(case, init, budget_s=12.0, single_s=6.0):
+    """The FP64 oracle on one instance of the workload, timed on all host
+    cores (the value) and on one core."""
     import oracle as O
 
-    sim = O.Sim(case.replace(precision="f64"), init_u=init)
-    sim.step(1)                      # page in, thread pool up
-    steps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        sim.step(2)
-        steps += 2
-    dt = time.perf_counter() - t0
-    return {"value": case.N * steps / dt / 1e6, "unit": "MLUPS", "cores": O.threads(),
+    def rate(seconds):
+        sim = O.Sim(case.replace(precision="f64"), init_u=init)
+        sim.step(1)                      # page in, thread pool up
+        steps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            sim.step(2)
+            steps += 2
+        return steps, time.perf_counter() - t0
+
+    cores = O.threads()
+    steps, dt = rate(budget_s)
+    O.set_threads(1)
+    steps1, dt1 = rate(single_s)
+    O.set_threads(cores)
+    return {"value": case.N * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"one instance of the sweep (De={case.target_De:g}, {case.N} nodes), "
-                      f"{steps} steps, {dt:.1f} s, FP64"}
+                      f"{steps} steps, {dt:.1f} s, FP64",
+            "single_core": {"value": case.N * steps1 / dt1 / 1e6, "unit": "MLUPS",
+                            "sample": f"the same instance, {steps1} steps, {dt1:.1f} s, one thread"}}
 
 
 def time_to_steady(n_train, n_test, tol=1e-6, cap=150000):

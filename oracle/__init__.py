@@ -75,6 +75,8 @@ def lib():
     L.orc_run_until.restype = C.c_double
     L.orc_cs2.restype = C.c_double
     L.orc_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = None
     _lib = L
     return L
 
@@ -223,6 +225,12 @@ class Sim:
 
 def threads():
     return lib().orc_threads()
+
+
+def set_threads(n: int):
+    """Threads of later oracle calls (n <= 0: all processors); results do not
+    depend on it."""
+    lib().orc_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------

@@ -760,3 +760,14 @@ int orc_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for later calls (n <= 0: all the processors the runtime sees).
+ * Results do not depend on it. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}

@@ -215,6 +215,21 @@ def test_step_nodes_matches_full_step():
     assert np.array_equal(out, full[:, nodes].T)
 
 
+def test_results_do_not_depend_on_the_thread_count():
+    """Each node's update is the same arithmetic whichever thread runs it."""
+    case = K.cylinder_case(0.9, 8, 4, 8, 0.8, De=10.0, walls3=True).replace(precision="f64")
+    init = K.perturbed_start(case, seed=3, amp=0.05, U_nom=0.05)
+    cores = O.threads()
+    out = []
+    for n in (1, max(2, cores)):
+        O.set_threads(n)
+        S = O.Sim(case, init_u=init)
+        S.step(40)
+        out.append(S.get_f())
+    O.set_threads(cores)
+    assert np.array_equal(out[0], out[1])
+
+
 def test_runs_are_bitwise_reproducible():
     case = K.cylinder_case(0.9, 8, 2, 8, 0.8, De=10.0, walls3=True)
     init = K.perturbed_start(case, seed=3, amp=0.05)
