@@ -136,6 +136,19 @@ mlbm_status mlbm_moments(mlbm_handle h, double *rho, double *u, int on_device);
  * Waits for the stream. */
 mlbm_status mlbm_vortex_intensity(mlbm_handle h, double *omega_mean, double *v_mean, double *De);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same observables as
+ * mlbm_vortex_intensity, bit for bit, computed with no device or host
+ * allocation on success.  Its working memory is a fixed 16 MiB device array
+ * inside the library, which each GPU the library runs on holds until the
+ * process ends; it fits instances of up to 3 N + 3 ceil(N / 256) + 3 <= 2^21
+ * doubles, i.e. N <= 696,000 nodes or so.  Larger instances get E_ARG and
+ * nothing is launched.  The array is shared by every call on the same GPU,
+ * so calls that overlap on one GPU (two host threads, or two streams) race
+ * and must be serialised by the caller.  Output pointers may be NULL.  Waits
+ * for the handle's stream.  Errors: E_ARG, E_HIP. */
+mlbm_status mlbm_vortex_intensity_noalloc(mlbm_handle h, double *omega_mean, double *v_mean, double *De);
+
 /* Residual of the last completed window: ||U_w - U_{w-1}|| / ||U_w|| over all
  * nodes and components (lattice units); -1 before two windows completed.
  * *bad receives the sticky instability flag.  Waits for the stream. */

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -63,8 +64,49 @@ struct GeoEntry {
 
 }  // namespace
 
+// Scratch of the allocation-free entry point (mlbm_vortex_intensity_noalloc):
+// a fixed device array that every GPU the library runs on holds until the
+// process ends. Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol); it uses the device address
+// that hipGetSymbolAddress returns for the current device, looked up once
+// per device at initialisation.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = size_t(1) << 21;   // 16 MiB
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// velocity [3][N], block triples [3][ceil(N / 256)] and three sums
+size_t noalloc_vortex_doubles(size_t N) { return 3 * N + 3 * ((N + 255) / 256) + 3; }
+
+// Device address of `scratch` on device `dev`, looked up on first use with
+// that device current (the library's init call does it for its device).
+mlbm_status noalloc_scratch(int dev, double **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(MLBM_E_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) HIP_TRY(hipSetDevice(cur));
+        HIP_TRY(e);
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MLBM_OK;
+}
+
+}  // namespace
+
 struct Batch {
     hipStream_t stream = nullptr;
+    int dev = 0;               // device the batch was created on
     bool own_stream = false;
     std::vector<Instance> inst;
     std::vector<GeoEntry> geos;
@@ -434,6 +476,15 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
         delete B;
         return fail(MLBM_E_HIP, "no HIP device");
     }
+    B->dev = dev;
+    {
+        double *p = nullptr;   // set-up of the allocation-free entry point for this device
+        mlbm_status ss = noalloc_scratch(dev, &p);
+        if (ss != MLBM_OK) {
+            delete B;
+            return ss;
+        }
+    }
     if (stream) {
         B->stream = (hipStream_t)stream;
     } else {
@@ -525,6 +576,25 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
 }
 
 Instance *inst_of(mlbm_handle h) { return (h && h->b) ? &h->b->inst[h->idx] : nullptr; }
+
+// <v_theta>, <omega> and the measured Dean number (Sec. III Eq. (8), Sec. IV)
+// from the sums over the cross sections of the v numerator, the omega
+// numerator and the area.
+void observables_from_sums(const Instance &I, double vs, double os, double as, double *omega_mean, double *v_mean,
+                           double *De)
+{
+    const mlbm_desc &d = I.desc;
+    const double vm = vs / as, om = os / as;
+    double de = 0.0;
+    if (d.kind != MLBM_FLAT) {
+        const double nu = (d.tau - 0.5) * CS2 * I.dt;
+        const double R = d.kind == MLBM_CYLINDER ? d.r_inner : d.r_inner * d.b * d.b;
+        de = vm * d.width / nu * std::sqrt(d.width / R);
+    }
+    if (omega_mean) *omega_mean = om;
+    if (v_mean) *v_mean = vm;
+    if (De) *De = de;
+}
 
 template <int I, int N, class F>
 void static_for_host(F &&f)
@@ -817,16 +887,37 @@ mlbm_status mlbm_vortex_intensity(mlbm_handle h, double *omega_mean, double *v_m
     HIP_TRY(hipStreamSynchronize(B->stream));
     double vs = 0.0, os = 0.0, as = 0.0;
     for (int k = 0; k < nblocks; ++k) { vs += part[3 * k]; os += part[3 * k + 1]; as += part[3 * k + 2]; }
-    const double vm = vs / as, om = os / as;
-    double de = 0.0;
-    if (d.kind != MLBM_FLAT) {
-        const double nu = (d.tau - 0.5) * CS2 * I->dt;
-        const double R = d.kind == MLBM_CYLINDER ? d.r_inner : d.r_inner * d.b * d.b;
-        de = vm * d.width / nu * std::sqrt(d.width / R);
-    }
-    if (omega_mean) *omega_mean = om;
-    if (v_mean) *v_mean = vm;
-    if (De) *De = de;
+    observables_from_sums(*I, vs, os, as, omega_mean, v_mean, De);
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_vortex_intensity_noalloc(mlbm_handle h, double *omega_mean, double *v_mean, double *De)
+{
+    Instance *I = inst_of(h);
+    if (!I) return fail(MLBM_E_ARG, "null handle");
+    Batch *B = h->b;
+    const size_t N = (size_t)I->hd.N;
+    const size_t nb = (N + 255) / 256;
+    const size_t need = noalloc_vortex_doubles(N);
+    if (need > NOALLOC_SCRATCH_DOUBLES)
+        return fail(MLBM_E_ARG, "mlbm_vortex_intensity_noalloc: " + std::to_string(N) + " nodes need " +
+                                    std::to_string(need * sizeof(double)) + " bytes of scratch, above the " +
+                                    std::to_string(NOALLOC_SCRATCH_DOUBLES * sizeof(double)) + "-byte maximum");
+    double *ptr = nullptr;
+    mlbm_status s = noalloc_scratch(B->dev, &ptr);
+    if (s != MLBM_OK) return s;
+    // velocity field [3][N], then the per-block triples, then the three sums;
+    // every element read is written earlier in the same call
+    double *du = ptr, *dpart = ptr + 3 * N, *dsum = dpart + 3 * nb;
+    HIP_TRY(launch_moments(B->d_insts + h->idx, I->hd, B->st, parity_of(*I), nullptr, du, B->stream));
+    int nblocks = 0;
+    const mlbm_desc &d = I->desc;
+    HIP_TRY(launch_vortex(I->hd, d.kind, d.b, I->dt * I->hd.s[0], I->dt * I->hd.s[2], du, dpart, &nblocks, B->stream));
+    HIP_TRY(launch_sum_partials(dpart, nblocks, dsum, B->stream));
+    double sums[3] = {0.0, 0.0, 0.0};
+    HIP_TRY(hipMemcpyAsync(sums, dsum, sizeof(sums), hipMemcpyDeviceToHost, B->stream));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    observables_from_sums(*I, sums[0], sums[1], sums[2], omega_mean, v_mean, De);
     return MLBM_OK;
 }
 

@@ -405,6 +405,24 @@ hipError_t launch_vortex(const InstDesc &h, int kind, double b, double h1, doubl
     return hipGetLastError();
 }
 
+// Sum of the per-block triples in block order by one lane: the same sequence
+// of FP64 additions as a host loop over the partials, hence the same bits.
+__global__ void sum_partials_kernel(const double *partials, int nb, double *out)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double a = 0.0, c = 0.0, e = 0.0;
+    for (int k = 0; k < nb; ++k) { a += partials[3 * k]; c += partials[3 * k + 1]; e += partials[3 * k + 2]; }
+    out[0] = a;
+    out[1] = c;
+    out[2] = e;
+}
+
+hipError_t launch_sum_partials(const double *partials, int nb, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------
 // Codecs: stored offsets (row-major storage order, pop_elem) <-> absolute
 // FP64 populations in the external layout [41][N]

@@ -47,6 +47,8 @@ hipError_t launch_moments(const InstDesc *d_desc, const InstDesc &h_desc, int st
 // observables: partial sums [blocks][3] of (v numerator, omega numerator, area)
 hipError_t launch_vortex(const InstDesc &h_desc, int kind, double b, double h1, double h3, const double *u,
                          double *partials, int *nblocks, hipStream_t s);
+// out[0..2] = sums of the partial triples over blocks 0..nb-1, in block order
+hipError_t launch_sum_partials(const double *partials, int nb, double *out, hipStream_t s);
 
 // decode (storage -> absolute FP64 f) and encode
 hipError_t launch_decode(const InstDesc &h_desc, int st, int parity, double *f, hipStream_t s);
