@@ -130,10 +130,12 @@ def test_laminar_cylinder_fp32_velocity_error(laminar_cylinder_oracle, prec):
 # Bounds are (velocity relative L2, Dean number relative error). FP32
 # (storage and arithmetic, with the exact mass/momentum bookkeeping of the
 # update) is held to the 1e-5 target. FP16 and BF16 offsets (per-row
-# reference, stochastic rounding) measure 2.6e-4 / 3e-5 and 2.0e-3 / 4e-5:
-# the FP16 bound is the 1e-3 target, the BF16 one 2.5x its measurement
-# (BF16 misses the target on this low-viscosity case).
-RP_BOUNDS = {"f32": (1e-5, 1e-5), "f32c64": (1e-5, 1e-5), "f16": (1e-3, 2e-4), "bf16": (5e-3, 2e-4)}
+# reference, stochastic rounding) are held to the 1e-3 target; they measure
+# 2.6e-4 / 3e-5 and 2.0e-3 / 4e-5, so BF16 misses the target on this
+# low-viscosity case and is marked as an expected failure.
+RP_BOUNDS = {"f32": (1e-5, 1e-5), "f32c64": (1e-5, 1e-5), "f16": (1e-3, 2e-4), "bf16": (1e-3, 2e-4)}
+BF16_MISSES = pytest.mark.xfail(strict=True, reason="BF16 offset storage misses the 1e-3 velocity target "
+                                                     "on the low-viscosity double-curved case (measured 2.0e-3)")
 
 
 @pytest.fixture(scope="module")
@@ -146,7 +148,7 @@ def ellipsoid_oracle():
     return case, init, o.moments()[1], o.observables()
 
 
-@pytest.mark.parametrize("prec", ["f32", "f32c64", "f16", "bf16"])
+@pytest.mark.parametrize("prec", ["f32", "f32c64", "f16", pytest.param("bf16", marks=BF16_MISSES)])
 def test_reduced_precision_velocity_and_dean_error(ellipsoid_oracle, prec):
     case, init, u_o, obs_o = ellipsoid_oracle
     g = mlbm.Sim(case.replace(precision=prec), init_u=init)
@@ -207,7 +209,7 @@ def test_cylinder_sweep_steady_states_fp32_against_fp64():
         assert err < 1e-5
 
 
-@pytest.mark.parametrize("prec,bound", [("f32", 1e-5), ("f16", 1e-3), ("bf16", 2e-3)])
+@pytest.mark.parametrize("prec,bound", [("f32", 1e-5), ("f16", 1e-3), ("bf16", 1e-3)])
 def test_reduced_precision_long_run_cylinder_sweep(prec, bound):
     """Curved-channel sweep instance (De = 45, 64 x 4 x 256, end walls) for 10 000 steps:
     FP32 and 16-bit storage against FP64 storage on the GPU (which matches

@@ -100,6 +100,95 @@ def test_rest_state_of_the_cylinder(eta, n1, tau):
     assert np.abs(u[1:]).max() < 1e-12
 
 
+@pytest.mark.parametrize("b2,R2,n1,tau", [
+    (1.0, 5.0, 16, 0.8), (1.0, 10.0, 16, 0.6), (1.0, 10.0, 32, 0.8),
+    (2.0, 5.0, 16, 0.8), (2.0, 10.0, 16, 0.6), (0.5, 5.0, 16, 0.8),
+])
+def test_rest_state_of_the_ellipsoid_slab(b2, R2, n1, tau):
+    """The double-curved slab (Sec. IV metric at theta = 0, rescaled spacings
+    of Sec. IV B) without force, started at rest, drains mass at the rate its
+    hydrostatic balance implies, derived as for the cylinder. At rest the
+    second moment is rho' c_s^2 g^jk, so the covariant momentum source is
+    S^m = -rho' c_s^2 (Gamma^m_jk g^jk + 2 Gamma^k_kj g^mj); the collision reads
+    U = -S / (2 rho'), and the mass source -2 rho' U^i Gamma^j_ji removes, with
+    the printed Christoffels (Gamma^r_tt = -r cos^2 phi, Gamma^r_pp = -r,
+    Gamma^t_rt = Gamma^p_rp = 1/r) and g^tt = 1/(r^2 b^2 cos^2 phi), near phi = 0
+        2 c_s^2 (3 - 1/b^2) / R^2 per step (R: radius in lattice units),
+    four times the cylinder's rate at b = 1. The phi Christoffels and the b
+    dependence of the centrifugal one both enter this rate, so it pins the
+    geometry of the slab together with its lattice rescaling and the
+    velocity reading. At b = 1 the radial velocity the collision reads is
+    (c_s^2 / 2)(3 - 1/b^2) / R."""
+    case = K.ellipsoid_case(R2 * b2, R2, n1, 2, 4, tau, De=None, precision="f64")
+    S = O.Sim(case)
+    S.step(300)
+    f0 = S.get_f()
+    m0 = f0.sum()
+    S.step(1000)
+    rate = math.log(m0 / S.get_f().sum()) / 1000
+    _, _, cs2, _ = O.lattice()
+    R = K.node_coords(case)[0] / case.dt
+    wts = f0.sum(axis=0).reshape(n1, -1).sum(axis=1)
+    pred = float((2.0 * cs2 * (3.0 - 1.0 / b2) / R ** 2 * wts).sum() / wts.sum())
+    print(f"b^2 {b2} R2 {R2} n1 {n1} tau {tau}: drain {rate:.4e} per step, predicted {pred:.4e}")
+    assert abs(rate / pred - 1.0) < 0.03
+    _, _, U = S.moments()
+    assert np.abs(U[1]).max() < 1e-14          # no streamwise flow without force
+    if b2 == 1.0:
+        ur = U[0].mean(axis=(1, 2)) / (cs2 / 2.0 * 2.0 / R)
+        assert np.all((ur > 0.8) & (ur < 1.05))
+
+
+def _shell_profile(r, ri, ro, K_phys, nu):
+    """Streamwise speed of laminar flow between concentric spheres near the
+    equator, driven by a constant covariant azimuthal force: with u^theta(r)
+    independent of the latitude the azimuthal Navier-Stokes balance reads
+    v'' + 2 v'/r - 2 v/r^2 = -K/(nu r) for v = r u^theta, solved by
+    v = -K/(3 nu) r ln r + B r + C / r^2 with v(r_i) = v(r_o) = 0."""
+    A = -K_phys / (3.0 * nu)
+    M = np.array([[ri, 1.0 / ri ** 2], [ro, 1.0 / ro ** 2]])
+    rhs = np.array([-A * ri * math.log(ri), -A * ro * math.log(ro)])
+    B, Cc = np.linalg.solve(M, rhs)
+    r = np.asarray(r, np.float64)
+    return A * r * np.log(r) + B * r + Cc / r ** 2
+
+
+@pytest.mark.parametrize("b2", [1.0, 2.0])
+def test_ellipsoid_slab_laminar_flow_tends_to_closed_form(b2):
+    """Laminar double-curved slab (16 x 1 x 4 around phi = 0, tau = 0.8, De 5)
+    at r_i/d = R2/d = 10, 20, 40: the streamwise speed r b cos(phi) u^theta
+    (the oracle's physical <-> lattice velocity conversion, u = s U with the
+    rescaled spacings of Sec. IV B) tends to the closed-form profile of the
+    equivalent spherical shell (b = 1: the slab's exact continuum problem;
+    b^2 = 2: the force matched through K / b, exact as d/R -> 0). The error
+    falls with d/R and stays at a third of the distance to plane Poiseuille
+    flow, so the curvature terms enter at first order in d/R; the mean speed
+    <v_theta> of Sec. IV (Sim.observables) follows the closed-form mean. A
+    misplaced factor b or r_i in the conversion or the force would be an
+    O(1) error at every radius."""
+    errs, mean_errs = [], []
+    for R2 in (10.0, 20.0, 40.0):
+        case = K.ellipsoid_case(R2 * b2, R2, 16, 1, 4, 0.8, De=5.0, precision="f64")
+        S = _steady(case, 1e-9, 60000)
+        r, ph = K.node_coords(case)
+        u = S.moments()[1]
+        v = (u[1] * (r[:, None, None] * case.b * np.cos(ph)[None, None, :])).mean(axis=(1, 2))
+        vs = _shell_profile(r, R2, R2 + 1.0, case.force / case.b, case.nu)
+        vflat = case.force / (case.b * R2) / (2 * case.nu) * (r - R2) * (R2 + 1.0 - r)
+        e_shell = np.linalg.norm(v - vs) / np.linalg.norm(vs)
+        e_flat = np.linalg.norm(v - vflat) / np.linalg.norm(vflat)
+        om, vm, De = S.observables()
+        mean_err = abs(vm / np.average(vs, weights=r) - 1.0)
+        print(f"b^2 {b2} R2 {R2}: shell {e_shell:.4e} flat {e_flat:.4e} mean {mean_err:.4e}")
+        assert e_shell < 0.45 * e_flat
+        errs.append(e_shell)
+        mean_errs.append(mean_err)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[0] < 0.025 and errs[2] < 0.008
+    assert mean_errs[0] > mean_errs[1] > mean_errs[2]
+    assert mean_errs[0] < 0.025 and mean_errs[2] < 0.008
+
+
 def _steady(case, tol=1e-10, max_steps=200000, init=None):
     S = O.Sim(case, init_u=K.poiseuille_field(case) if init is None else init)
     R, steps, bad = S.run_until(tol, 100, max_steps)
@@ -142,11 +231,23 @@ def curved_errors():
 
 def test_curved_poiseuille_approaches_closed_form_as_curvature_drops(curved_errors):
     """The laminar profile tends to u_theta = A r ln r + B r + C / r with
-    A = -K / (2 nu) as d / R -> 0 (model error of the scheme scales with the
-    curvature)."""
+    A = -K / (2 nu) as d / R -> 0.  The remaining error is a model error of the
+    scheme as printed (velocity read without a half-force shift; it does not
+    fall with the force, see the next test, nor with N_r): 1.86 %, 0.83 % and
+    0.63 % at eta = 0.9, 0.95, 0.975 (N_r = 16, tau = 0.8), held here within
+    8 % of those values so that any change to the curvature terms shows."""
     e = [curved_errors[(eta, 0)] for eta in (0.9, 0.95, 0.975)]
     assert e[0] > e[1] > e[2]
-    assert e[0] < 0.025 and e[2] < 0.01
+    for got, ref in zip(e, (0.01857, 0.00834, 0.00632)):
+        assert abs(got / ref - 1.0) < 0.08, (got, ref)
+
+
+def test_curved_poiseuille_error_is_not_a_compressibility_error(curved_errors):
+    """Halving the force (and so the Mach number) leaves the closed-form error
+    unchanged to 3 %: it is not an O(Ma^2) effect of the driving."""
+    e5 = curved_errors[(0.9, 0)]
+    e25 = _curved_err(0.9, De=2.5)
+    assert abs(e25 / e5 - 1.0) < 0.03
 
 
 def test_improved_forcing_beats_old_forcing(curved_errors):
