@@ -69,7 +69,7 @@ typedef enum {
  * grouped into calls, batches or graphs. mlbm_set_populations and the
  * initial state round to nearest. */
 
-enum { MLBM_WALL_AXIS1 = 1, MLBM_WALL_AXIS3 = 4 };
+enum { MLBM_WALL_AXIS1 = 1, MLBM_WALL_AXIS3 = 4, MLBM_WALL_EQUILIBRIUM = 8 };
 enum { MLBM_FORCING_IMPROVED = 0, MLBM_FORCING_OLD = 1 };
 
 /* Problem description, following the paper's statement of the problem
@@ -79,13 +79,22 @@ enum { MLBM_FORCING_IMPROVED = 0, MLBM_FORCING_OLD = 1 };
  *  n1, n2, n3    nodes along r, theta, z/phi; each >= 1, an axis with walls
  *                needs >= 4 nodes.
  *  walls         bit mask of MLBM_WALL_AXIS1 / MLBM_WALL_AXIS3; axes without
- *                walls (and axis 2 always) are periodic.  Walls are halfway:
- *                half a spacing outside the first and last node.
+ *                walls (and axis 2 always) are periodic.  Walls are halfway
+ *                bounce-back walls, half a spacing outside the first and
+ *                last node (Dt = Dr = d / n1).  With MLBM_WALL_EQUILIBRIUM
+ *                (needs MLBM_WALL_AXIS1 and a periodic axis 3) the axis-1
+ *                walls are instead the Dirichlet walls of Sec. III: the
+ *                first and last x1 rows are wall nodes at r_i and r_o
+ *                (Dt = Dr = d / (n1 - 1)), set every step to f_eq(rho',
+ *                u = 0) with rho' the density streamed into them; they do
+ *                not collide, a pull from beyond a wall node reads the wall
+ *                node, and their velocity is reported as 0.
  *  forcing_mode  MLBM_FORCING_IMPROVED (a2 = a2_eq - sigma) or MLBM_FORCING_OLD.
  *  precision     mlbm_precision.
  *  check_every   K, steps per stationarity window (even, >= 2); 0 means 100.
  *  r_inner       inner radius r_i (ignored for MLBM_FLAT).
- *  width         channel width d = r_o - r_i; Dt = Dr = d / n1.
+ *  width         channel width d = r_o - r_i; Dt = Dr = d / n1 (bounce-back)
+ *                or d / (n1 - 1) (equilibrium walls).
  *  b             ellipsoid semi-axis b (streamwise curvature radius r_i b^2).
  *  tau           BGK relaxation parameter, > 0.5.
  *  force         covariant streamwise body force K (physical units); the

@@ -30,6 +30,13 @@
  *     centred, the walls sit half a spacing outside the first and last node.
  *     A population whose backward straight path leaves the domain is traced
  *     back through full velocity reversals at every wall it meets.
+ *   - equilibrium (Dirichlet) walls of Sec. III, on request for the r axis
+ *     (x3 then periodic): the first and last x1 rows are wall nodes at r_i
+ *     and r_o, Dr = d / (n1 - 1); each step a wall node is set to
+ *     f_eq(rho', u = 0) with rho' the density of the populations streamed
+ *     into it, and it does not collide; the region beyond a wall is at rest
+ *     in that same state, i.e. a pull from beyond the wall reads the wall
+ *     node.  Velocities at wall nodes are zero (the Dirichlet value).
  *   - the external force is a constant covariant theta component K, so its
  *     contravariant form is g^{i theta} K.
  *   - the ellipsoidal slab is streamwise periodic with the metric frozen at
@@ -46,6 +53,9 @@
  *   - geometry: Christoffels equal the Levi-Civita connection of the metric
  *     and of the embedding, lattice rescaling, covariant force, streaming with
  *     bounce-back is a permutation, hand-worked bounce-back paths;
+ *   - equilibrium walls: plane Poiseuille flow between them converges to the
+ *     parabola through zero velocity at the wall nodes, and the cylinder's
+ *     laminar profile to the curved closed form;
  *   - flow: uniform flow is a fixed point, a shear wave decays with
  *     nu = cs2 (tau - 1/2), plane Poiseuille converges at second order, the
  *     curved profile tends to its closed form, the mass budget closes each
@@ -343,10 +353,14 @@ void orc_metric(int kind, double b, double x1, double x2, double x3,
 /* Simulation                                                               */
 /* ------------------------------------------------------------------------ */
 
+#define ORC_WALL_EQ 8   /* axis-1 walls are equilibrium walls with wall nodes */
+
 typedef struct {
     int kind;           /* ORC_FLAT, ORC_CYLINDER, ORC_ELLIPSOID                 */
     int n1, n2, n3;     /* nodes along r (x), theta (y), z/phi (z)               */
-    int walls;          /* bit 0: walls on axis 1, bit 2: walls on axis 3        */
+    int walls;          /* bit 0: walls on axis 1, bit 2: walls on axis 3,
+                           bit 3 (ORC_WALL_EQ): the axis-1 walls are
+                           equilibrium walls (Sec. III) instead of bounce-back */
     int forcing_mode;   /* 0 improved, 1 old                                     */
     double r_inner;     /* inner radius r_i (cylinder, ellipsoid)                */
     double width;       /* channel width d = r_o - r_i                           */
@@ -372,6 +386,12 @@ typedef struct {
     long t;
 } orc_sim;
 
+/* Is x1 a wall-node row of an equilibrium wall? */
+static int is_wall_row(const orc_case *c, int x1)
+{
+    return (c->walls & ORC_WALL_EQ) && (x1 == 0 || x1 == c->n1 - 1);
+}
+
 static long node_index(const orc_case *c, int x1, int x2, int x3)
 {
     return ((long)x1 * c->n2 + x2) * c->n3 + x3;
@@ -391,6 +411,17 @@ static int wrap(int v, int n)
 static void pull_source(const orc_case *cs, const int x[3], int q, int src[3], int *qsrc)
 {
     const int n[3] = {cs->n1, cs->n2, cs->n3};
+    if (cs->walls & ORC_WALL_EQ) {
+        /* wall nodes at both ends of axis 1, at rest beyond them: a source
+         * beyond a wall node is that wall node; the other axes are periodic */
+        for (int a = 0; a < 3; ++a) {
+            int v = x[a] - LC[q][a];
+            if (a == 0) src[a] = v < 0 ? 0 : (v > n[0] - 1 ? n[0] - 1 : v);
+            else src[a] = wrap(v, n[a]);
+        }
+        *qsrc = q;
+        return;
+    }
     const int walled[3] = {cs->walls & 1, 0, (cs->walls >> 2) & 1};
     int m = 0;
     for (int a = 0; a < 3; ++a) { int v = abs(LC[q][a]); if (v > m) m = v; }
@@ -423,15 +454,18 @@ static void geometry_point(const orc_sim *S, int x1, int x3, double out_coord[3]
 {
     const orc_case *c = &S->cs;
     const double dr = S->dt * S->s[0];
+    /* cell centred between halfway walls, or on the nodes r_i + x1 Dr whose
+     * first and last are the equilibrium walls (Sec. III node placement) */
+    const double o1 = (c->walls & ORC_WALL_EQ) ? 0.0 : 0.5;
     double a1 = 0.0, a3 = 0.0;
     if (c->kind == ORC_FLAT) {
-        a1 = (x1 + 0.5) * dr;
+        a1 = (x1 + o1) * dr;
         a3 = (x3 + 0.5) * S->dt * S->s[2];
     } else if (c->kind == ORC_CYLINDER) {
-        a1 = c->r_inner + (x1 + 0.5) * dr;                 /* r, cell centred      */
+        a1 = c->r_inner + (x1 + o1) * dr;                  /* r                    */
         a3 = (x3 + 0.5) * S->dt * S->s[2];                  /* z                    */
     } else {
-        a1 = c->r_inner + (x1 + 0.5) * dr;                  /* r                    */
+        a1 = c->r_inner + (x1 + o1) * dr;                   /* r                    */
         a3 = (x3 + 0.5 - 0.5 * c->n3) * S->dt * S->s[2];    /* phi, symmetric about 0 */
     }
     out_coord[0] = a1; out_coord[1] = 0.0; out_coord[2] = a3;
@@ -468,7 +502,9 @@ orc_sim *orc_create(const orc_case *cs, const double *init_u)
     S->cs = *cs;
     S->N = (long)cs->n1 * cs->n2 * cs->n3;
     S->NX = (long)cs->n1 * cs->n3;
-    S->dt = cs->width / cs->n1;                      /* Dt = Dr = d / N_r */
+    /* Dt = Dr = d / N_r: N_r fluid nodes between halfway walls, or n1 - 1
+     * spacings between the wall nodes of equilibrium walls */
+    S->dt = cs->width / ((cs->walls & ORC_WALL_EQ) ? cs->n1 - 1 : cs->n1);
     S->s[0] = 1.0; S->s[1] = 1.0; S->s[2] = 1.0;
     if (cs->kind == ORC_ELLIPSOID) {                 /* rescaled spacings of Sec. IV B */
         S->s[1] = 1.0 / (cs->b * cs->r_inner);
@@ -502,7 +538,7 @@ orc_sim *orc_create(const orc_case *cs, const double *init_u)
             for (int x3 = 0; x3 < cs->n3; ++x3) {
                 long n = node_index(cs, x1, x2, x3), p = (long)x1 * cs->n3 + x3;
                 double U[3] = {0, 0, 0};
-                if (init_u)
+                if (init_u && !is_wall_row(cs, x1))
                     for (int i = 0; i < 3; ++i) U[i] = init_u[i * S->N + n] / S->s[i];
                 orc_feq(1.0 / S->sqrtg[p], U, S->ginv + 9 * p, S->f + n * Q);
             }
@@ -529,16 +565,31 @@ static long xsec_of(const orc_sim *S, long n)
     return x1 * S->cs.n3 + x3;
 }
 
+static int row_of(const orc_sim *S, long n) { return (int)(n / ((long)S->cs.n2 * S->cs.n3)); }
+
+/* Post-step state of node n from its streamed populations: BGK with forcing
+ * (Eq. (3)), or at an equilibrium-wall node f_eq(rho', u = 0) (Sec. III). */
+static void update_node(const orc_sim *S, long n, const double fin[Q], double out[Q])
+{
+    const long p = xsec_of(S, n);
+    if (is_wall_row(&S->cs, row_of(S, n))) {
+        double rho = 0.0;
+        for (int q = 0; q < Q; ++q) rho += fin[q];
+        const double zero[3] = {0.0, 0.0, 0.0};
+        orc_feq(rho, zero, S->ginv + 9 * p, out);
+        return;
+    }
+    collide_node(fin, S->ginv + 9 * p, S->gam + 27 * p, S->fext + 3 * p, S->cs.tau, S->cs.forcing_mode, out);
+}
+
 void orc_step(orc_sim *S, long nsteps)
 {
     for (long it = 0; it < nsteps; ++it) {
 #pragma omp parallel for schedule(static)
         for (long n = 0; n < S->N; ++n) {
             double fin[Q];
-            long p = xsec_of(S, n);
             gather(S, S->f, n, fin);
-            collide_node(fin, S->ginv + 9 * p, S->gam + 27 * p, S->fext + 3 * p,
-                         S->cs.tau, S->cs.forcing_mode, S->fn + n * Q);
+            update_node(S, n, fin, S->fn + n * Q);
         }
         double *t = S->f; S->f = S->fn; S->fn = t;
         S->t++;
@@ -553,14 +604,13 @@ void orc_step_nodes(const orc_sim *S, const double *state_qn, const long *nodes,
 {
 #pragma omp parallel for schedule(static)
     for (long k = 0; k < count; ++k) {
-        long n = nodes[k], p = xsec_of(S, n);
+        long n = nodes[k];
         double fin[Q];
         for (int q = 0; q < Q; ++q) {
             long slot = S->pull[n * Q + q];
             fin[q] = state_qn[(slot % Q) * S->N + slot / Q];
         }
-        collide_node(fin, S->ginv + 9 * p, S->gam + 27 * p, S->fext + 3 * p,
-                     S->cs.tau, S->cs.forcing_mode, out + k * Q);
+        update_node(S, n, fin, out + k * Q);
     }
 }
 
@@ -594,7 +644,8 @@ void orc_geometry(const orc_sim *S, double *ginv, double *gcov, double *sqrtg, d
 
 /* Moments of the streamed state (what the next collision sees):
  * rho' = sum f, rho' U = sum c f (Sec. II); returned as rho = rho' sqrt(g)
- * and the physical contravariant velocity u^i = s_i U^i (layout [i][node]).
+ * and the physical contravariant velocity u^i = s_i U^i (layout [i][node]);
+ * U = 0 at the wall nodes of equilibrium walls.
  * lat_u, if given, receives U (lattice units, [i][node]). */
 void orc_moments(const orc_sim *S, double *rho, double *u, double *lat_u)
 {
@@ -607,9 +658,10 @@ void orc_moments(const orc_sim *S, double *rho, double *u, double *lat_u)
             for (int i = 0; i < 3; ++i) j[i] += LC[q][i] * fin[q];
         }
         long p = xsec_of(S, n);
+        const int wall = is_wall_row(&S->cs, row_of(S, n));
         if (rho) rho[n] = r * S->sqrtg[p];
         for (int i = 0; i < 3; ++i) {
-            double U = j[i] / r;
+            double U = wall ? 0.0 : j[i] / r;   /* the Dirichlet value at a wall node */
             if (u) u[i * S->N + n] = S->s[i] * U;
             if (lat_u) lat_u[i * S->N + n] = U;
         }
@@ -619,14 +671,21 @@ void orc_moments(const orc_sim *S, double *rho, double *u, double *lat_u)
 double orc_cs2(void) { build_lattice(); return CS2; }
 
 /* Derivative along a lattice axis of a cross-section field v[x1][x3] at one
- * theta slab, in physical units: second-order central differences; next to
- * a wall the one-sided second-order formula through the wall value v = 0 at
- * half a spacing; periodic wrap on axes without walls. */
+ * theta slab, in physical units: second-order central differences; with
+ * halfway walls (walled = 1) next to a wall the one-sided second-order
+ * formula through the wall value v = 0 at half a spacing; with wall nodes
+ * (walled = 2, equilibrium walls) the one-sided second-order formula at the
+ * wall node itself; periodic wrap on axes without walls. */
 static double ddx(const double *v, int n1, int n3, int axis, int walled, int x1, int x3, double h)
 {
     int n = axis == 0 ? n1 : n3, x = axis == 0 ? x1 : x3;
 #define V(a, c) v[(long)(a) * n3 + (c)]
 #define AT(k) (axis == 0 ? V(k, x3) : V(x1, k))
+    if (walled == 2) {
+        if (x == 0) return (-3.0 * AT(0) + 4.0 * AT(1) - AT(2)) / (2.0 * h);
+        if (x == n - 1) return (3.0 * AT(n - 1) - 4.0 * AT(n - 2) + AT(n - 3)) / (2.0 * h);
+        return (AT(x + 1) - AT(x - 1)) / (2.0 * h);
+    }
     if (walled) {
         if (n == 1) return 0.0;
         if (x == 0) return (AT(0) + AT(1) / 3.0) / h;
@@ -647,7 +706,9 @@ static double ddx(const double *v, int n1, int n3, int axis, int walled, int x1,
  *              S = int r dr dphi; flat: unweighted mean of |d_3 u^1 - d_1 u^3|.
  *   De = <v_theta> d / nu * sqrt(d / R), nu = (tau - 1/2) cs2 Dt,
  *        R = r_i (cylinder), R_theta = r_i b^2 (ellipsoid); 0 for flat space.
- * Averages over the theta slabs. */
+ * Averages over the theta slabs.  With equilibrium walls the integrals over
+ * r run over the wall nodes with the trapezoidal rule (half weight at r_i
+ * and r_o). */
 void orc_observables_u(const orc_sim *S, const double *u, double *omega_mean, double *v_mean,
                        double *De)
 {
@@ -669,16 +730,18 @@ void orc_observables_u(const orc_sim *S, const double *u, double *omega_mean, do
             for (int x3 = 0; x3 < n3; ++x3) {
                 long p = (long)x1 * n3 + x3, n = node_index(c, x1, x2, x3);
                 const double r = S->coord[3 * p], ph = S->coord[3 * p + 2];
+                const int eq = (c->walls & ORC_WALL_EQ) != 0;
                 double d3ur = ddx(ur, n1, n3, 2, (c->walls >> 2) & 1, x1, x3, h3);
-                double d1uz = ddx(uz, n1, n3, 0, c->walls & 1, x1, x3, h1);
+                double d1uz = ddx(uz, n1, n3, 0, eq ? 2 : (c->walls & 1), x1, x3, h1);
+                const double tw = is_wall_row(c, x1) ? 0.5 : 1.0;   /* trapezoidal weight */
                 double vort = fabs(d3ur - d1uz), uth = u[1 * N + n];
                 double wv, wo, ws;
                 if (c->kind == ORC_CYLINDER) { wv = r; wo = r; ws = 1.0; }
                 else if (c->kind == ORC_ELLIPSOID) { wv = r * r * c->b * cos(ph); wo = r * c->b * cos(ph); ws = r; }
                 else { wv = 1.0; wo = 1.0; ws = 1.0; }
-                v_num += uth * wv * h1 * h3;
-                om_num += vort * wo * h1 * h3;
-                area += ws * h1 * h3;
+                v_num += tw * uth * wv * h1 * h3;
+                om_num += tw * vort * wo * h1 * h3;
+                area += tw * ws * h1 * h3;
             }
     }
     *v_mean = v_num / area;

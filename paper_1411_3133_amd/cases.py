@@ -32,6 +32,10 @@ KINDS = ("flat", "cylinder", "ellipsoid")
 PRECISIONS = ("f64", "f32", "f16", "bf16", "f32c64")
 WALL_AXIS1 = 1
 WALL_AXIS3 = 4
+# The axis-1 walls are the equilibrium (Dirichlet) walls of Sec. III: the
+# first and last x1 rows are wall nodes at r_i and r_o, so n1 - 1 spacings
+# span the channel (x3 must then be periodic).
+WALL_EQ = 8
 
 
 @dataclasses.dataclass
@@ -57,8 +61,12 @@ class Case:
         return self.n1 * self.n2 * self.n3
 
     @property
+    def eq_walls(self) -> bool:
+        return bool(self.walls & WALL_EQ)
+
+    @property
     def dt(self) -> float:
-        return self.width / self.n1
+        return self.width / (self.n1 - 1 if self.eq_walls else self.n1)
 
     @property
     def nu(self) -> float:
@@ -175,9 +183,10 @@ def uniform_pm1(seed: int, count: int, stream: int = 0) -> np.ndarray:
 # --------------------------------------------------------------------------
 
 def node_coords(case: Case):
-    """Physical (x1, x3) of the cross-section nodes, [n1], [n3] (cell centred)."""
+    """Physical (x1, x3) of the cross-section nodes, [n1], [n3]: cell centred
+    between halfway walls, or on r_i + x1 Dr with equilibrium walls."""
     dt = case.dt
-    x1 = (np.arange(case.n1) + 0.5) * dt
+    x1 = (np.arange(case.n1) + (0.0 if case.eq_walls else 0.5)) * dt
     if case.kind != "flat":
         x1 = case.r_inner + x1
     if case.kind == "ellipsoid":
@@ -234,9 +243,13 @@ def perturbed_start(case: Case, seed: int, amp: float = 1e-4,
 
 def cylinder_case(eta: float, n1: int, n2: int, n3: int, tau: float, De: Optional[float] = None,
                   walls3: bool = False, precision: str = "f64", forcing_mode: int = 0,
-                  label: str = "") -> Case:
-    """Streamwise-curved channel of Sec. III: r_i = 1, d = (1 - eta) / eta."""
-    c = Case(kind="cylinder", n1=n1, n2=n2, n3=n3, walls=WALL_AXIS1 | (WALL_AXIS3 if walls3 else 0),
+                  label: str = "", eq_walls: bool = False) -> Case:
+    """Streamwise-curved channel of Sec. III: r_i = 1, d = (1 - eta) / eta.
+    eq_walls: the equilibrium walls of Sec. III (n1 includes the two wall rows)."""
+    if eq_walls and walls3:
+        raise ValueError("equilibrium walls need a periodic x3 axis")
+    c = Case(kind="cylinder", n1=n1, n2=n2, n3=n3,
+             walls=WALL_AXIS1 | (WALL_AXIS3 if walls3 else 0) | (WALL_EQ if eq_walls else 0),
              r_inner=1.0, width=(1.0 - eta) / eta, b=1.0, tau=tau, precision=precision,
              forcing_mode=forcing_mode, target_De=De, label=label)
     if De is not None:
@@ -245,10 +258,13 @@ def cylinder_case(eta: float, n1: int, n2: int, n3: int, tau: float, De: Optiona
 
 
 def ellipsoid_case(R1: float, R2: float, n1: int, n2: int, n3: int, tau: float,
-                   De: Optional[float] = None, precision: str = "f32", label: str = "") -> Case:
+                   De: Optional[float] = None, precision: str = "f32", label: str = "",
+                   eq_walls: bool = False) -> Case:
     """Double-curved channel of Sec. IV with d = 1: r_i = R2 (= R_phi),
-    b^2 = R1 / R2 (so R_theta = r_i b^2 = R1), periodic phi sector."""
-    c = Case(kind="ellipsoid", n1=n1, n2=n2, n3=n3, walls=WALL_AXIS1, r_inner=R2, width=1.0,
+    b^2 = R1 / R2 (so R_theta = r_i b^2 = R1), periodic phi sector.
+    eq_walls: the equilibrium walls of Sec. III (n1 includes the two wall rows)."""
+    c = Case(kind="ellipsoid", n1=n1, n2=n2, n3=n3, walls=WALL_AXIS1 | (WALL_EQ if eq_walls else 0),
+             r_inner=R2, width=1.0,
              b=math.sqrt(R1 / R2), tau=tau, precision=precision, target_De=De, label=label)
     if De is not None:
         c.force = nominal_force(c, De)

@@ -58,7 +58,7 @@ struct Instance {
 struct GeoEntry {
     double *ptr = nullptr;
     float *fptr = nullptr;     // the same values rounded to FP32
-    int kind, n1, n3;
+    int kind, n1, n3, eq;
     double r_inner, width, b;
 };
 
@@ -154,7 +154,10 @@ mlbm_status validate(const mlbm_desc &d)
 {
     if (d.kind < 0 || d.kind > 2) return fail(MLBM_E_ARG, "kind must be MLBM_FLAT, MLBM_CYLINDER or MLBM_ELLIPSOID");
     if (d.n1 < 1 || d.n2 < 1 || d.n3 < 1) return fail(MLBM_E_ARG, "n1, n2, n3 must be >= 1");
-    if ((d.walls & ~(MLBM_WALL_AXIS1 | MLBM_WALL_AXIS3)) != 0) return fail(MLBM_E_ARG, "walls: unknown bits");
+    if ((d.walls & ~(MLBM_WALL_AXIS1 | MLBM_WALL_AXIS3 | MLBM_WALL_EQUILIBRIUM)) != 0)
+        return fail(MLBM_E_ARG, "walls: unknown bits");
+    if ((d.walls & MLBM_WALL_EQUILIBRIUM) && (d.walls & (MLBM_WALL_AXIS1 | MLBM_WALL_AXIS3)) != MLBM_WALL_AXIS1)
+        return fail(MLBM_E_ARG, "equilibrium walls need walls on axis 1 and a periodic axis 3");
     if ((d.walls & MLBM_WALL_AXIS1) && d.n1 < 4) return fail(MLBM_E_ARG, "an axis with walls needs >= 4 nodes (n1)");
     if ((d.walls & MLBM_WALL_AXIS3) && d.n3 < 4) return fail(MLBM_E_ARG, "an axis with walls needs >= 4 nodes (n3)");
     const double N = (double)d.n1 * d.n2 * d.n3;
@@ -178,9 +181,13 @@ mlbm_status validate(const mlbm_desc &d)
     return MLBM_OK;
 }
 
+bool eq_walls(const mlbm_desc &d) { return (d.walls & MLBM_WALL_EQUILIBRIUM) != 0; }
+
 void scales(const mlbm_desc &d, double &dt, double s[3])
 {
-    dt = d.width / d.n1;
+    // N_r fluid nodes between halfway walls, or n1 - 1 spacings between the
+    // wall nodes of equilibrium walls
+    dt = d.width / (eq_walls(d) ? d.n1 - 1 : d.n1);
     s[0] = s[1] = s[2] = 1.0;
     if (d.kind == MLBM_ELLIPSOID) {   // rescaled spacings of Sec. IV B
         s[1] = 1.0 / (d.b * d.r_inner);
@@ -387,7 +394,7 @@ GeoEntry *find_or_make_geo(Batch *B, const mlbm_desc &d, int &key, mlbm_status &
     for (size_t k = 0; k < B->geos.size(); ++k) {
         GeoEntry &g = B->geos[k];
         if (g.kind == d.kind && g.n1 == d.n1 && g.n3 == d.n3 && g.r_inner == d.r_inner && g.width == d.width &&
-            g.b == d.b) {
+            g.b == d.b && g.eq == (int)eq_walls(d)) {
             key = (int)k;
             st = MLBM_OK;
             return &g;
@@ -395,6 +402,7 @@ GeoEntry *find_or_make_geo(Batch *B, const mlbm_desc &d, int &key, mlbm_status &
     }
     GeoEntry g{};
     g.kind = d.kind; g.n1 = d.n1; g.n3 = d.n3; g.r_inner = d.r_inner; g.width = d.width; g.b = d.b;
+    g.eq = (int)eq_walls(d);
     const int n3g = d.kind == MLBM_ELLIPSOID ? d.n3 : 1;
     hipError_t e = hipMalloc(&g.ptr, sizeof(double) * NGEO * d.n1 * n3g);
     if (e != hipSuccess) {
@@ -403,6 +411,7 @@ GeoEntry *find_or_make_geo(Batch *B, const mlbm_desc &d, int &key, mlbm_status &
     }
     GeoParams p{};
     p.kind = d.kind; p.n1 = d.n1; p.n3 = d.n3; p.n3g = n3g;
+    p.eqwall = (int)eq_walls(d);
     p.r_inner = d.r_inner; p.width = d.width; p.b = d.b;
     scales(d, p.dt, p.s);
     e = launch_geometry(g.ptr, p, B->stream);
@@ -522,6 +531,7 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
         h.geo = g->ptr;
         h.geof = g->fptr;
         h.n1 = d.n1; h.n2 = d.n2; h.n3 = d.n3; h.walls = d.walls;
+        h.eqwall = (int)eq_walls(d);
         h.P = d.n2 * d.n3;
         h.N = d.n1 * h.P;
         h.n3g = d.kind == MLBM_ELLIPSOID ? d.n3 : 1;
@@ -706,6 +716,7 @@ mlbm_status mlbm_pull_map(const mlbm_desc *d, int64_t *src_node, int32_t *src_q)
     if (s != MLBM_OK) return s;
     InstDesc h{};
     h.n1 = d->n1; h.n2 = d->n2; h.n3 = d->n3; h.walls = d->walls;
+    h.eqwall = (int)eq_walls(*d);
     h.P = d->n2 * d->n3;
     h.N = d->n1 * h.P;
     for (int x1 = 0; x1 < d->n1; ++x1)

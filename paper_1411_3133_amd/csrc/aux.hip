@@ -21,21 +21,24 @@ __global__ void geometry_kernel(double *geo, GeoParams p)
     if (idx >= NX) return;
     const int x1 = idx / p.n3g, x3 = idx - x1 * p.n3g;
     const double dt = p.dt;
+    // nodes cell centred between halfway walls, or on r_i + x1 Dr whose first
+    // and last are the wall nodes of equilibrium walls (Sec. III)
+    const double o1 = p.eqwall ? 0.0 : 0.5;
     double X1, X3;
     double g11 = 1.0, g22 = 1.0, g33 = 1.0;
     double G[3][3][3] = {};
     if (p.kind == 0) {                        // flat
-        X1 = (x1 + 0.5) * dt * p.s[0];
+        X1 = (x1 + o1) * dt * p.s[0];
         X3 = (x3 + 0.5) * dt * p.s[2];
     } else if (p.kind == 1) {                 // cylinder (r, theta, z)
-        const double r = p.r_inner + (x1 + 0.5) * dt * p.s[0];
+        const double r = p.r_inner + (x1 + o1) * dt * p.s[0];
         X1 = r;
         X3 = (x3 + 0.5) * dt * p.s[2];
         g22 = r * r;
         G[0][1][1] = -r;                      // Gamma^r_{theta theta}
         G[1][0][1] = G[1][1][0] = 1.0 / r;    // Gamma^theta_{r theta}
     } else {                                  // ellipsoid (r, theta, phi), a = c = 1, theta = 0
-        const double r = p.r_inner + (x1 + 0.5) * dt * p.s[0];
+        const double r = p.r_inner + (x1 + o1) * dt * p.s[0];
         const double ph = (x3 + 0.5 - 0.5 * p.n3) * dt * p.s[2];
         const double cp = cos(ph), sp = sin(ph);
         X1 = r;
@@ -111,7 +114,8 @@ __device__ void init_offsets(const InstDesc &d, int n, const double *init_u, dou
     D[1][2] = D[2][1] = geo[G_D23 * NX + gi];
     const double rho = 1.0 / geo[G_SQRTG * NX + gi];
     double U[3] = {0.0, 0.0, 0.0};
-    if (init_u)
+    const bool wall = d.eqwall && (x1 == 0 || x1 == d.n1 - 1);   // at rest (Dirichlet)
+    if (init_u && !wall)
         for (int i = 0; i < 3; ++i) U[i] = init_u[(size_t)i * d.N + n] / d.s[i];
     const double cs2 = CS2;
     const double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
@@ -315,6 +319,7 @@ __global__ void moments_kernel(const InstDesc *dd, int parity, double *rho, doub
     pull_f64<ST>(d, parity, x1, x2, x3, g);
     double r, U[3];
     moments_only<double>(g, r, U);
+    if (d.eqwall && (x1 == 0 || x1 == d.n1 - 1)) U[0] = U[1] = U[2] = 0.0;   // Dirichlet value
     const int NX = d.n1 * d.n3g;
     const int gi = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
     if (rho) rho[n] = r * d.geo[G_SQRTG * NX + gi];
@@ -343,8 +348,15 @@ hipError_t launch_moments(const InstDesc *d_desc, const InstDesc &h, int st, int
 // wall the one-sided second-order formula through u = 0 at the halfway wall.
 // ------------------------------------------------------------------------
 
-__device__ __forceinline__ double ddx_axis(const double *f, int stride, int x, int n, bool walled, double h)
+// walled: 0 periodic, 1 halfway walls, 2 wall nodes (equilibrium walls: the
+// one-sided second-order formula at the wall node itself)
+__device__ __forceinline__ double ddx_axis(const double *f, int stride, int x, int n, int walled, double h)
 {
+    if (walled == 2) {
+        if (x == 0) return (-3.0 * f[0] + 4.0 * f[stride] - f[2 * stride]) / (2.0 * h);
+        if (x == n - 1) return (3.0 * f[0] - 4.0 * f[-stride] + f[-2 * stride]) / (2.0 * h);
+        return (f[stride] - f[-stride]) / (2.0 * h);
+    }
     if (walled) {
         if (n == 1) return 0.0;
         if (x == 0) return (f[0] + f[stride] / 3.0) / h;
@@ -368,16 +380,18 @@ __global__ void vortex_kernel(InstDesc d, int kind, double b, double h1, double 
         const int gi = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
         const double r = d.geo[G_X1 * NX + gi], ph = d.geo[G_X3 * NX + gi];
         const double *ur = u + n, *uz = u + 2 * (size_t)d.N + n;
-        const double d3ur = ddx_axis(ur, 1, x3, d.n3, (d.walls & 4) != 0, h3);
-        const double d1uz = ddx_axis(uz, d.P, x1, d.n1, (d.walls & 1) != 0, h1);
+        const double d3ur = ddx_axis(ur, 1, x3, d.n3, (d.walls & 4) ? 1 : 0, h3);
+        const double d1uz = ddx_axis(uz, d.P, x1, d.n1, d.eqwall ? 2 : ((d.walls & 1) ? 1 : 0), h1);
+        // trapezoidal weight over r with wall nodes at r_i and r_o
+        const double tw = (d.eqwall && (x1 == 0 || x1 == d.n1 - 1)) ? 0.5 : 1.0;
         const double vort = fabs(d3ur - d1uz);
         const double uth = u[(size_t)d.N + n];
         double wv = 1.0, wo = 1.0, ws = 1.0;
         if (kind == 1) { wv = r; wo = r; }
         else if (kind == 2) { const double cp = cos(ph); wv = r * r * b * cp; wo = r * b * cp; ws = r; }
-        vs = uth * wv * h1 * h3;
-        os = vort * wo * h1 * h3;
-        as = ws * h1 * h3;
+        vs = tw * uth * wv * h1 * h3;
+        os = tw * vort * wo * h1 * h3;
+        as = tw * ws * h1 * h3;
     }
     for (int off = 32; off > 0; off >>= 1) {
         vs += __shfl_xor(vs, off, 64);
@@ -503,7 +517,10 @@ __global__ void step_nodes_kernel(const InstDesc *dd, int parity, const int64_t 
     NodeGeo<PAT, C> geo;
     geo.load(d.geo, d.geof, x1 * d.n3g + (d.n3g > 1 ? x3 : 0), d.n1 * d.n3g, (C)d.force);
     C rho, u[3];
-    collide<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
+    if (d.eqwall && (x1 == 0 || x1 == d.n1 - 1))
+        wall_equilibrium<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, rho);
+    else
+        collide<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
     static_for<0, Q>([&](auto q) {
         // round through the storage format, as the step kernel stores it
         const float r = Codec<ST>::REF ? d.ref[x1 * Q + q] : 0.0f;

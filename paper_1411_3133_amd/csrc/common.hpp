@@ -49,6 +49,7 @@ struct InstDesc {
     uint32_t *ctr;         // FP16/BF16 storage: step counter [2] (read [parity], next in [parity ^ 1])
     uint32_t salt;         // per-instance key of the stochastic rounding
     int n1, n2, n3, walls;
+    int eqwall;            // 1: the x1 walls are equilibrium walls (wall-node rows 0 and n1 - 1)
     int P, N;              // n2*n3, n1*n2*n3
     int n3g;               // 1 or n3
     int tpr;               // tiles per x1 row

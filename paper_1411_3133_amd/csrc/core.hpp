@@ -353,6 +353,36 @@ __device__ __forceinline__ void moments_only(const C (&g)[Q], C &rho_out, C (&u_
     static_for<0, 3>([&](auto I) { u_out[I] = j[I] * ir; });
 }
 
+// Equilibrium (Dirichlet) wall node of Sec. III: the streamed populations
+// only give the density rho'; the node is set to f_eq(rho', u = 0), i.e.
+// f/w - 1 = (rho' - 1) + rho' (c Delta c - cs2 tr Delta) / (2 cs2), and does
+// not collide. Register conventions as in collide().
+template <int PAT, class C, class R, bool SCALED = false>
+__host__ __device__ __forceinline__ void wall_equilibrium(R (&g)[Q], const NodeGeo<PAT, C> &G, C &rho_out)
+{
+    constexpr auto ws = [](int q) constexpr { return SCALED ? C(wq(q)) : C(1); };
+    C m0 = ws(0) * (C)g[0];
+    static_for<1, Q>([&](auto q) { m0 += ws(q) * (C)g[q]; });
+    const C rho = C(1) + m0;
+    C trD = C(-0.0);
+    static_for<0, 3>([&](auto I) { if constexpr (Mask<PAT>::D(I, I)) trD += G.D[I][I]; });
+    const C half_ics2 = (C)(0.5 / CS2);
+    static_for<0, Q>([&](auto q) {
+        C cDc = C(-0.0);
+        static_for<0, 3>([&](auto I) {
+            static_for<0, 3>([&](auto J) {
+                constexpr int cc = CV[q][I] * CV[q][J];
+                if constexpr (cc != 0 && Mask<PAT>::D(I, J))
+                    cDc += C(cc) * G.D[I < J ? I : J][I < J ? J : I];
+            });
+        });
+        const C h = m0 + rho * (half_ics2 * cDc - C(0.5) * trD);   // f / w - 1
+        if constexpr (SCALED) g[q] = (R)h;
+        else g[q] = (R)(C(wq(q)) * h);
+    });
+    rho_out = rho;
+}
+
 // ------------------------------------------------------------------------
 // Streaming
 // ------------------------------------------------------------------------
@@ -460,6 +490,9 @@ __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, 
     for (int k = 0; k < 5; ++k) {
         int r1 = x1 - CVALS[k];
         if (per1) r1 = wrap_axis(r1, d.n1);
+        // equilibrium walls: the region beyond a wall node is at rest in the
+        // wall node's state, so a pull from beyond it reads the wall node
+        if (d.eqwall) r1 = r1 < 0 ? 0 : (r1 > d.n1 - 1 ? d.n1 - 1 : r1);
         rows[k] = r1;
         rb[k] = (uint64_t)r1 * (uint64_t)Q * PS;
     }
@@ -610,6 +643,12 @@ __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, i
         return x2 * d.n3 + x3;
     } else {
         constexpr int h1 = C1 / m, h2 = C2 / m, h3 = C3 / m;
+        if (d.eqwall) {   // wall nodes on axis 1 (clamped pull), x3 periodic
+            int s1 = x1 - C1;
+            s1 = s1 < 0 ? 0 : (s1 > d.n1 - 1 ? d.n1 - 1 : s1);
+            row = s1;
+            return wrap_axis(x2 - C2, d.n2) * d.n3 + wrap_axis(x3 - C3, d.n3);
+        }
         int back = 1 << 28, front = 1 << 28;
         if constexpr (C1 != 0) {
             if (d.walls & 1) {

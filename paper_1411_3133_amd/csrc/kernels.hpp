@@ -20,6 +20,7 @@ hipError_t launch_step(const StepArgs &a, int pat, int st, bool check, int grid,
 // geometry of one instance (FP64, on the device)
 struct GeoParams {
     int kind, n1, n3, n3g;
+    int eqwall;    // node placement of equilibrium walls (wall nodes at r_i, r_o)
     double r_inner, width, b, dt, s[3];
 };
 hipError_t launch_geometry(double *geo, const GeoParams &p, hipStream_t s);

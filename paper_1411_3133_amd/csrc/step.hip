@@ -13,6 +13,10 @@
 // of queued tiles is read from device memory so that a captured graph stays
 // valid when instances retire.
 //
+// With equilibrium walls (Sec. III) the first and last x1 rows are wall
+// nodes: pulls from beyond them read the wall row, and a wall row is set to
+// the equilibrium at zero velocity instead of colliding.
+//
 // The CHECK variant (every K-th step) also writes the lattice velocity the
 // collision used to the snapshot buffer and reduces, per tile, the squared
 // change against the previous snapshot, the squared velocity and an
@@ -53,7 +57,10 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
                 gstore<uint32_t>(d.ctr, 4ull * (uint32_t)(a.parity ^ 1), ctr + 1u);
         }
 
-        const bool wall1_row = (d.walls & 1) && (x1 < 3 || x1 > d.n1 - 4);
+        // bounce-back rows within reach of an x1 wall; equilibrium walls pull
+        // through clamped rows in the fast gather instead
+        const bool wall1_row = (d.walls & 1) && !d.eqwall && (x1 < 3 || x1 > d.n1 - 4);
+        const bool eq_row = d.eqwall && (x1 == 0 || x1 == d.n1 - 1);   // a wall-node row
         const bool near3 = valid && (d.walls & 4) && (x3 < 3 || x3 > d.n3 - 4);
         const bool any3 = __ballot(near3) != 0;
 
@@ -79,7 +86,12 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
             NodeGeo<PAT, C> geo;
             geo.load(d.geo, d.geof, gidx, d.n1 * d.n3g, (C)d.force);
             C rho, u[3];
-            collide<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
+            if (eq_row) {
+                wall_equilibrium<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, rho);
+                u[0] = u[1] = u[2] = C(0);
+            } else {
+                collide<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, (C)d.omega, (C)d.kappa, rho, u);
+            }
             const size_t n = (size_t)x1 * d.P + col;
             void *drow = (char *)dst + pop_elem(0, x1, 0, d.P) * S;
             const uint32_t loff = (uint32_t)col * S;

@@ -55,6 +55,17 @@ def test_kernel_streaming_fold_equals_oracle_pull_map(n1, n2, n3, walls):
     assert np.array_equal(src * 41 + sq, pm)
 
 
+@pytest.mark.parametrize("n1,n2,n3", list(itertools.product([4, 5, 7, 16], [1, 3], [1, 4, 6])))
+def test_kernel_streaming_fold_with_equilibrium_walls_equals_oracle(n1, n2, n3):
+    """Equilibrium walls (Sec. III): a pull from beyond a wall node reads the
+    wall node; the kernels' fold and the oracle's pull map agree."""
+    case = K.Case(kind="flat", n1=n1, n2=n2, n3=n3, walls=K.WALL_AXIS1 | K.WALL_EQ, width=1.0)
+    src, sq = mlbm.pull_map(case)
+    assert np.array_equal(sq, np.broadcast_to(np.arange(41), sq.shape))   # never reflected
+    pm = O.Sim(case).pull_map()
+    assert np.array_equal(src * 41 + sq, pm)
+
+
 def test_kernel_streaming_fold_at_benchmark_sizes():
     for case in (K.laminar_cylinder(), K.cylinder_sweep(De_values=[40.0])[0], K.ellipsoid_96x192_cases()[0]):
         src, sq = mlbm.pull_map(case)
@@ -64,7 +75,8 @@ def test_kernel_streaming_fold_at_benchmark_sizes():
 
 
 @pytest.mark.parametrize("bad", [
-    dict(n1=0), dict(tau=0.5), dict(tau=0.3), dict(width=0.0), dict(walls=8),
+    dict(n1=0), dict(tau=0.5), dict(tau=0.3), dict(width=0.0), dict(walls=8), dict(walls=1 | 4 | 8),
+    dict(walls=16),
     dict(n1=3), dict(check_every=3), dict(precision="f64", forcing_mode=2),
     dict(kind="ellipsoid", b=0.0), dict(kind="ellipsoid", n3=4000, b=1.0),
     # largest sizes: a population buffer of 4 GiB or more, and a cross
