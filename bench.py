@@ -1,17 +1,22 @@
 """Benchmark of the fused metric lattice Boltzmann step on one MI355X.
 
-Workload (default): the curved-channel sweep near transition -- cylinder
-64 x 4 x 256 nodes, eta = 0.975, no-slip end walls, De = 30, 31, ..., 60 by
-body force (31 instances, 2,031,616 nodes), populations stored and collided
-in FP32, closed-form laminar start plus a seeded 1e-4 perturbation.  One step
-is one time step of every instance, issued by the batched kernel in K-step
-graph windows with the fused residual check.
+Workload (default): the batched parameter sweep -- 64 double-curved channel
+instances (ellipsoid slabs of Sec. IV at R1/d = 20) of 8 curvature pairs with
+R2/R1 log-uniform in [0.25, 4], per-pair grids N_r 45..96 x 4 x N_phi 64..246
+drawn from seed 3133 (3.04 M nodes), De uniform in [20, 200], populations
+stored and collided in FP32, closed-form laminar start plus a seeded 1e-4
+perturbation.  One step is one time step of every instance, issued by the
+persistent batched kernel in K-step graph windows with the fused residual
+check.  Pairs whose tau (Mach rule) lies under the measured stability floor
+are run as drawn and named in `health`.
 
 Prints one JSON line: throughput in MLUPS (million lattice updates per
 second over all instances), the HBM roofline of the step kernel
 (algorithmic bytes 2 * 41 * S per update, S = bytes per stored population,
 over the device time per step measured with HIP events on the stream the
-kernel runs on) and the FP64 CPU oracle timed on the host cores.
+kernel runs on), side legs (the cylinder sweep, one instance beyond the
+last-level cache, time to steady, critical Dean numbers) and the FP64 CPU
+oracle timed on the host cores.
 """
 import argparse
 import hashlib
@@ -43,7 +48,7 @@ def kernel_source_digest(read=None):
             with open(os.path.join(ROOT, "paper_1411_3133_amd", "csrc", fn)) as f:
                 return f.read()
     h = hashlib.sha256()
-    for fn in ("core.hpp", "step.hip", "common.hpp", "lattice.hpp"):
+    for fn in ("core.hpp", "step_kernel.hpp", "step.hip", "common.hpp", "lattice.hpp"):
         h.update(_code_only(read(fn)).encode())
     return h.hexdigest()[:16]
 
@@ -83,8 +88,8 @@ def cpu_baseline(case, init, budget_s=12.0, single_s=6.0):
     O.set_threads(cores)
     return {"value": case.N * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
-            "sample": f"one instance of the sweep (De={case.target_De:g}, {case.N} nodes), "
-                      f"{steps} steps, {dt:.1f} s, FP64",
+            "sample": f"one instance of the workload ({case.label}: {case.n1}x{case.n2}x{case.n3}, "
+                      f"De={case.target_De:.1f}, {case.N} nodes), {steps} steps, {dt:.1f} s, FP64",
             "single_core": {"value": case.N * steps1 / dt1 / 1e6, "unit": "MLUPS",
                             "sample": f"the same instance, {steps1} steps, {dt1:.1f} s, one thread"}}
 
@@ -150,38 +155,80 @@ def time_to_steady(n_train, n_test, tol=1e-6, cap=150000):
     }
 
 
-def uneven_batch_leg(precision, steps=1000, warmup=200, block=0, grid=0):
-    """Throughput of the persistent kernel on the uneven ellipsoid batch: 64
-    double-curved instances of 8 curvature pairs (N_r 45..96, N_phi 64..240,
-    2.9 M nodes), one launch per step over all of them, autotuned launch,
-    HIP-event time per step on the batch stream."""
+def timed_batch(cases, inits, steps, warmup, block=0, grid=0):
+    """Run `cases` as one batch on torch's current stream: autotuned (or the
+    given) launch, `warmup` untimed steps rounded up to whole check windows
+    (so the timed region starts on a window boundary and runs as captured
+    K-step graphs), then `steps` timed steps bracketed by device
+    synchronisations. Returns the batch (still open) and the timings."""
     import torch
-    from paper_1411_3133_amd import cases as K
     from paper_1411_3133_amd import mlbm
 
-    cases = K.uneven_ellipsoid_batch(precision=precision)
-    inits = [K.perturbed_start(c, seed=3133 + i, amp=1e-4) for i, c in enumerate(cases)]
     b = mlbm.Batch(cases, inits, stream=torch.cuda.current_stream())
     if block:
         b.set_launch(block, grid)
     else:
         block, grid = b.autotune(steps=50)
-    b.step(warmup)
+    K = cases[0].check_every
+    warm = -(-warmup // K) * K if steps >= K else warmup
+    b.step(warm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.step(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = b.last_step_ms()
-    nodes = sum(c.N for c in cases)
+    windows, eager = divmod(steps, K) if warm % K == 0 else (0, steps)
+    launch = {"block": block, "grid": grid, "check_every": K, "graph_windows_timed": windows,
+              "eager_steps_timed": eager, "warmup_steps": warm}
+    return b, wall, ev_ms, launch
+
+
+def batch_health(b, cases):
+    """Residual and instability flag of every instance after the timed steps,
+    and the instances whose tau lies under the measured stability floor."""
+    from paper_1411_3133_amd import cases as K
+
+    res = [b[i].residual() for i in range(len(cases))]
+    unstable = [cases[i].label for i in range(len(cases)) if res[i][1]]
+    below = sorted({c.label.split("-k")[0] for c in cases if K.below_stability_floor(c)})
+    return {"unstable_instances": unstable, "max_residual": max(r[0] for r in res),
+            "checks_done": any(r[0] >= 0 for r in res), "below_stability_floor": below}
+
+
+def uneven_batch_headline(precision, steps, warmup, block=0, grid=0):
+    """The headline workload: the batched parameter sweep of 64 uneven
+    double-curved instances, one launch per step over all of them."""
+    from paper_1411_3133_amd import cases as K
+
+    cases = K.uneven_ellipsoid_batch(precision=precision)
+    inits = [K.perturbed_start(c, seed=3133 + i, amp=1e-4) for i, c in enumerate(cases)]
+    b, wall, ev_ms, launch = timed_batch(cases, inits, steps, warmup, block, grid)
+    health = batch_health(b, cases)
     b.close()
+    return cases, inits, wall, ev_ms, launch, health
+
+
+def cylinder_sweep_leg(precision, steps=2000, warmup=200, block=0, grid=0):
+    """The curved-channel sweep near transition: cylinder 64 x 4 x 256,
+    eta = 0.975, end walls, De 30..60 (31 instances, 2.0 M nodes)."""
+    from paper_1411_3133_amd import cases as K
+
+    cases = K.cylinder_sweep(precision=precision)
+    inits = [K.perturbed_start(c, seed=1411 + i, amp=1e-4) for i, c in enumerate(cases)]
+    b, wall, ev_ms, launch = timed_batch(cases, inits, steps, warmup, block, grid)
+    health = batch_health(b, cases)
+    b.close()
+    nodes = sum(c.N for c in cases)
     alg = 2 * 41 * BYTES[precision] * nodes
-    return {"workload": "uneven ellipsoid batch: 64 ellipsoid slabs, 8 curvature pairs (R2/R1 0.25..4, N_r 45..96, "
-                        "N_phi 64..240), De 20..200, 1e-4 perturbation",
-            "nodes": nodes, "storage": precision, "launch": {"block": block, "grid": grid},
+    achieved = alg / (ev_ms * 1e-3) / 1e9
+    return {"workload": "curved-channel sweep: cylinder 64x4x256, eta=0.975, end walls, De=30..60 "
+                        "(31 instances), laminar start + 1e-4 perturbation",
+            "nodes": nodes, "storage": precision, "tau": cases[0].tau, "launch": launch,
             "MLUPS": round(nodes * steps / wall / 1e6, 1),
-            "achieved_GBs": round(alg / (ev_ms * 1e-3) / 1e9, 1),
-            "frac": round(alg / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "achieved_GBs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(f"cylinder_sweep_64x4x256_{precision}", kernel_source_digest()),
+            "health": health}
 
 
 def beyond_cache_leg(precision, steps=500, warmup=100, block=0, grid=0):
@@ -206,7 +253,7 @@ def beyond_cache_leg(precision, steps=500, warmup=100, block=0, grid=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ev_ms = b.last_step_ms()
-    bad = b[0].residual()[1]
+    health = batch_health(b, [case])
     b.close()
     alg = 2 * 41 * BYTES[precision] * case.N
     return {"workload": f"ellipsoid 96x{case.n2}x192 (R1/d=20, R2/d=40, De=60), one instance, "
@@ -216,7 +263,7 @@ def beyond_cache_leg(precision, steps=500, warmup=100, block=0, grid=0):
             "MLUPS": round(case.N * steps / wall / 1e6, 1),
             "achieved_GBs": round(alg / (ev_ms * 1e-3) / 1e9, 1),
             "frac": round(alg / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "unstable": bool(bad)}
+            "health": health}
 
 
 def critical_dean_leg(tol=1e-7):
@@ -281,9 +328,12 @@ def main():
                     help="unseen cases in the time-to-steady leg (0 skips it)")
     ap.add_argument("--steady-train", type=int, default=500, help="training fields for the warm start")
     ap.add_argument("--critical", type=int, default=1, help="run the critical-De leg (0 skips it)")
-    ap.add_argument("--uneven", type=int, default=1, help="time the uneven ellipsoid batch (0 skips it)")
+    ap.add_argument("--sweep", type=int, default=1, help="time the cylinder sweep as a side leg (0 skips it)")
     ap.add_argument("--beyond-cache", type=int, default=1,
                     help="time one instance larger than the last-level cache (0 skips it)")
+    ap.add_argument("--only", choices=["sweep", "beyond"], default=None,
+                    help="time only the cylinder sweep or the beyond-cache instance and print its leg "
+                         "(for profiling one kernel on one workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -304,41 +354,24 @@ def main():
 
     import torch
 
-    from paper_1411_3133_amd import cases as K
-    from paper_1411_3133_amd import mlbm
-
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    cases = K.cylinder_sweep(precision=args.precision)
-    inits = [K.perturbed_start(c, seed=1411 + i, amp=1e-4) for i, c in enumerate(cases)]
-    batch = mlbm.Batch(cases, inits, stream=stream)
+    if args.only == "sweep":
+        print(json.dumps(cylinder_sweep_leg(args.precision, args.steps, args.warmup, args.block, args.grid)))
+        return
+    if args.only == "beyond":
+        print(json.dumps(beyond_cache_leg(args.precision, args.steps, args.warmup, args.block, args.grid)))
+        return
+    cases, inits, wall, ev_ms, launch, health = uneven_batch_headline(
+        args.precision, args.steps, args.warmup, args.block, args.grid)
     nodes = sum(c.N for c in cases)
-    block, grid = (256, 0)
-    if args.block:
-        block, grid = args.block, args.grid
-        batch.set_launch(block, grid)
-    elif not args.no_autotune:
-        block, grid = batch.autotune(steps=100)
-    batch.step(args.warmup)
-    torch.cuda.synchronize()
-    # timed region
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batch.step(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = batch.last_step_ms()
-    res = [batch[i].residual()[0] for i in range(len(cases))]
-    bad = any(batch[i].residual()[1] for i in range(len(cases)))
-
     ms_per_step = wall * 1e3 / args.steps
     value = nodes * args.steps / wall / 1e6
     S = BYTES[args.precision]
     alg_bytes = 2 * 41 * S * nodes
     achieved = alg_bytes / (ev_ms * 1e-3) / 1e9
     digest = kernel_source_digest()
-    tag = f"cylinder_sweep_64x4x256_{args.precision}"
-    traffic = measured_traffic(tag, digest)
+    traffic = measured_traffic(f"uneven_ellipsoid_batch_{args.precision}", digest)
+    pairs = sorted({c.label.split("-k")[0] for c in cases})
     line = {
         "metric": "MLUPS & % HBM peak; time-to-steady per case, warm/batched vs plain at 1e-6",
         "value": round(value, 1),
@@ -353,11 +386,12 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {
-            "workload": "curved-channel sweep: cylinder 64x4x256, eta=0.975, end walls, "
-                        "De=30..60 (31 instances), laminar start + 1e-4 perturbation",
-            "instances": len(cases), "nodes": nodes, "storage": args.precision,
-            "tau": cases[0].tau, "check_every": cases[0].check_every,
-            "launch": {"block": block, "grid": grid, "hipgraph_window": cases[0].check_every},
+            "workload": "batched parameter sweep: 64 double-curved channel instances (ellipsoid slabs, "
+                        "R1/d=20, 8 curvature pairs with R2/R1 log-uniform in [0.25,4], per-pair N_r 45..96 x 4 x "
+                        "N_phi 64..246 drawn from seed 3133, De uniform in [20,200], tau per pair from the Mach "
+                        "rule), one persistent launch per step, K-step hipGraph windows, 1e-4 perturbation",
+            "instances": len(cases), "pairs": len(pairs), "nodes": nodes, "storage": args.precision,
+            "launch": launch,
         },
         "roofline": {
             "bound": "hbm",
@@ -366,16 +400,15 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "step_kernel (fused stream/collide, HIP events per step)",
+            "kernel": "step_kernel (fused stream/collide, HIP events per step on the batch stream)",
             "alg_bytes_per_step": alg_bytes,
             "event_ms_per_step": round(ev_ms, 5),
             "kernel_source_digest": digest,
         },
-        "health": {"unstable": bad, "max_residual": max(res)},
+        "health": health,
     }
-    batch.close()
-    if args.uneven:
-        line["uneven_batch"] = uneven_batch_leg(args.precision, block=args.block, grid=args.grid)
+    if args.sweep:
+        line["cylinder_sweep"] = cylinder_sweep_leg(args.precision, block=args.block, grid=args.grid)
     if args.beyond_cache:
         line["beyond_cache"] = beyond_cache_leg(args.precision, block=args.block, grid=args.grid)
     if args.steady > 0:
@@ -383,7 +416,7 @@ def main():
     if args.critical:
         line["critical_dean"] = critical_dean_leg()
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(cases[15], inits[15])
+        line["cpu_baseline"] = cpu_baseline(cases[0], inits[0])
     print(json.dumps(line), flush=True)
 
 

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlbm.so")
-SOURCES = ["step.hip", "aux.hip", "api.hip", "mlp.hip"]
+SOURCES = ["step.hip", "step_eq.hip", "aux.hip", "api.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

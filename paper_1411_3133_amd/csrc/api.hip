@@ -111,6 +111,7 @@ struct Batch {
     std::vector<Instance> inst;
     std::vector<GeoEntry> geos;
     int st = ST_F64, pat = PAT_CYL, K = 100;
+    bool eqw = false;          // some instance has equilibrium walls (kernel variant)
     int block = 256, grid = 0;
     bool use_graph = true;
     int num_cu = 256;
@@ -150,6 +151,14 @@ namespace {
 
 int pattern_for_kind(int kind) { return kind == MLBM_ELLIPSOID ? PAT_ELL : PAT_CYL; }
 
+// Storage pitch of x3: n3 rounded up to 16 values, so that every x2 row of
+// every population plane starts on a 64-byte boundary (measured on the
+// batched ellipsoid sweep: an instance with n3 = 113 stepped at 44 % of the
+// HBM peak, at n3 = 112 at 64 %).
+int x3_pitch(int n3) { return (n3 + 15) / 16 * 16; }
+
+size_t storage_values(const InstDesc &h) { return (size_t)Q * h.n1 * h.Pp; }
+
 mlbm_status validate(const mlbm_desc &d)
 {
     if (d.kind < 0 || d.kind > 2) return fail(MLBM_E_ARG, "kind must be MLBM_FLAT, MLBM_CYLINDER or MLBM_ELLIPSOID");
@@ -160,10 +169,12 @@ mlbm_status validate(const mlbm_desc &d)
         return fail(MLBM_E_ARG, "equilibrium walls need walls on axis 1 and a periodic axis 3");
     if ((d.walls & MLBM_WALL_AXIS1) && d.n1 < 4) return fail(MLBM_E_ARG, "an axis with walls needs >= 4 nodes (n1)");
     if ((d.walls & MLBM_WALL_AXIS3) && d.n3 < 4) return fail(MLBM_E_ARG, "an axis with walls needs >= 4 nodes (n3)");
-    const double N = (double)d.n1 * d.n2 * d.n3;
-    if (N * Q * (double)storage_bytes(d.precision < 0 || d.precision > 4 ? 0 : d.precision) >= 4294967296.0)
-        return fail(MLBM_E_ARG, "one population buffer must stay below 4 GiB (41 N bytes-per-value)");
-    if ((double)d.n2 * d.n3 >= (double)(1 << 20)) return fail(MLBM_E_ARG, "n2 * n3 must be < 2^20");
+    const double Np = (double)d.n1 * d.n2 * x3_pitch(d.n3);
+    if (Np * Q * (double)storage_bytes(d.precision < 0 || d.precision > 4 ? 0 : d.precision) >= 4294967296.0)
+        return fail(MLBM_E_ARG, "one population buffer must stay below 4 GiB (41 n1 n2 n3p bytes-per-value, "
+                                "n3p = n3 rounded up to 16)");
+    if ((double)d.n2 * x3_pitch(d.n3) >= (double)(1 << 20))
+        return fail(MLBM_E_ARG, "n2 * n3 (n3 rounded up to 16) must be < 2^20");
     if (d.forcing_mode != MLBM_FORCING_IMPROVED && d.forcing_mode != MLBM_FORCING_OLD)
         return fail(MLBM_E_ARG, "forcing_mode must be MLBM_FORCING_IMPROVED or MLBM_FORCING_OLD");
     if (d.precision < 0 || d.precision > 4) return fail(MLBM_E_ARG, "precision out of range");
@@ -245,7 +256,7 @@ mlbm_status build_tiles(Batch *B)
     std::vector<int> pb(B->inst.size(), -1), pc(B->inst.size(), 0);
     for (size_t i = 0; i < B->inst.size(); ++i) {
         Instance &I = B->inst[i];
-        I.hd.tpr = (I.hd.P + B->block - 1) / B->block;
+        I.hd.tpr = (I.hd.Pp + B->block - 1) / B->block;
         if (!I.active) continue;
         pb[i] = (int)tiles.size();
         for (int x1 = 0; x1 < I.hd.n1; ++x1)
@@ -289,7 +300,7 @@ mlbm_status enqueue_step(Batch *B, bool check)
 {
     if (B->ntiles == 0) return MLBM_OK;
     StepArgs a{B->d_insts, B->d_tiles, B->d_ntiles, B->d_partials, (int)(B->t & 1)};
-    HIP_TRY(launch_step(a, B->pat, B->st, check, launch_grid(B), B->block, B->stream));
+    HIP_TRY(launch_step(a, B->pat, B->st, check, B->eqw, launch_grid(B), B->block, B->stream));
     if (check) HIP_TRY(launch_reduce(B->d_partials, B->d_pb, B->d_pc, B->d_ws, (int)B->inst.size(), B->stream));
     B->t += 1;
     for (auto &I : B->inst)
@@ -465,12 +476,14 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
     if (!ds || n < 1 || !out) return fail(MLBM_E_ARG, "null description or n < 1");
     const int K = ds[0].check_every ? ds[0].check_every : 100;
     int pat = PAT_CYL;
+    bool eqw = false;
     for (int i = 0; i < n; ++i) {
         mlbm_status s = validate(ds[i]);
         if (s != MLBM_OK) return fail(s, "instance " + std::to_string(i) + ": " + g_err);
         if (ds[i].precision != ds[0].precision) return fail(MLBM_E_ARG, "every instance of a batch needs the same precision");
         if ((ds[i].check_every ? ds[i].check_every : 100) != K) return fail(MLBM_E_ARG, "every instance needs the same check_every");
         pat = std::max(pat, pattern_for_kind(ds[i].kind));
+        eqw |= eq_walls(ds[i]);
     }
     if (const char *e = getenv("MLBM_PATTERN")) {   // compile-time sparsity override (tests of the general kernel)
         if (!strcmp(e, "general")) pat = PAT_GEN;
@@ -479,6 +492,7 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
     B->st = ds[0].precision;
     B->K = K;
     B->pat = pat;
+    B->eqw = eqw;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&B->num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
@@ -534,17 +548,21 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
         h.eqwall = (int)eq_walls(d);
         h.P = d.n2 * d.n3;
         h.N = d.n1 * h.P;
+        h.n3p = x3_pitch(d.n3);
+        h.Pp = d.n2 * h.n3p;
         h.n3g = d.kind == MLBM_ELLIPSOID ? d.n3 : 1;
-        h.n3_magic = ((1ull << 40) + (uint64_t)d.n3 - 1) / (uint64_t)d.n3;
+        h.n3_magic = ((1ull << 40) + (uint64_t)h.n3p - 1) / (uint64_t)h.n3p;
         h.omega = 1.0 / d.tau;
         h.kappa = d.forcing_mode == MLBM_FORCING_IMPROVED ? 1.0 - 1.0 / (2.0 * d.tau) : 0.0;
         h.force = d.force;
         scales(d, I.dt, h.s);
-        const size_t fb = sbytes * (size_t)Q * h.N;
+        const size_t fb = sbytes * storage_values(h);
         if (hipMalloc(&h.f[0], fb) != hipSuccess || hipMalloc(&h.f[1], fb) != hipSuccess ||
             hipMalloc(&h.usnap, sizeof(double) * 3 * (size_t)h.N) != hipSuccess)
             return bail(fail(MLBM_E_OOM, "population allocation failed (instance " + std::to_string(i) + ")"));
-        if (hipMemsetAsync(h.usnap, 0, sizeof(double) * 3 * (size_t)h.N, B->stream) != hipSuccess)
+        if (hipMemsetAsync(h.usnap, 0, sizeof(double) * 3 * (size_t)h.N, B->stream) != hipSuccess ||
+            hipMemsetAsync(h.f[0], 0, fb, B->stream) != hipSuccess ||   // the x3 padding stays zero
+            hipMemsetAsync(h.f[1], 0, fb, B->stream) != hipSuccess)
             return bail(fail(MLBM_E_HIP, "hipMemsetAsync failed"));
         h.ref = nullptr;
         h.ctr = nullptr;
@@ -719,6 +737,8 @@ mlbm_status mlbm_pull_map(const mlbm_desc *d, int64_t *src_node, int32_t *src_q)
     h.eqwall = (int)eq_walls(*d);
     h.P = d->n2 * d->n3;
     h.N = d->n1 * h.P;
+    h.n3p = d->n3;              // the host map is in node indices: no padding
+    h.Pp = h.P;
     for (int x1 = 0; x1 < d->n1; ++x1)
         for (int x2 = 0; x2 < d->n2; ++x2)
             for (int x3 = 0; x3 < d->n3; ++x3) {
@@ -982,7 +1002,7 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
     for (size_t i = 0; i < B->inst.size(); ++i) {
         Instance &I = B->inst[i];
         if (!I.active) continue;
-        const size_t bytes = sb * Q * (size_t)I.hd.N;
+        const size_t bytes = sb * storage_values(I.hd);
         hipError_t e = hipMalloc(&backup[i], bytes);
         if (e == hipSuccess)
             e = hipMemcpyAsync(backup[i], I.hd.f[parity_of(I)], bytes, hipMemcpyDeviceToDevice, B->stream);
@@ -1012,7 +1032,7 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
             StepArgs a{B->d_insts, B->d_tiles, B->d_ntiles, B->d_partials, 0};
             for (int k = 0; k < 4 * steps; ++k) {
                 a.parity = (int)((t_keep + k) & 1);
-                if (launch_step(a, B->pat, B->st, false, launch_grid(B), B->block, B->stream) != hipSuccess) st = MLBM_E_HIP;
+                if (launch_step(a, B->pat, B->st, false, B->eqw, launch_grid(B), B->block, B->stream) != hipSuccess) st = MLBM_E_HIP;
             }
         }
     }
@@ -1025,14 +1045,14 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
             StepArgs a{B->d_insts, B->d_tiles, B->d_ntiles, B->d_partials, 0};
             for (int k = 0; k < 2; ++k) {
                 a.parity = (int)((t_keep + k) & 1);
-                if (launch_step(a, B->pat, B->st, false, launch_grid(B), B->block, B->stream) != hipSuccess) st = MLBM_E_HIP;
+                if (launch_step(a, B->pat, B->st, false, B->eqw, launch_grid(B), B->block, B->stream) != hipSuccess) st = MLBM_E_HIP;
             }
             float cand = 1e30f;
             for (int rep = 0; rep < 3; ++rep) {
                 if (hipEventRecord(B->ev0, B->stream) != hipSuccess) st = MLBM_E_HIP;
                 for (int k = 0; k < steps; ++k) {
                     a.parity = (int)((t_keep + k) & 1);
-                    if (launch_step(a, B->pat, B->st, false, launch_grid(B), B->block, B->stream) != hipSuccess) st = MLBM_E_HIP;
+                    if (launch_step(a, B->pat, B->st, false, B->eqw, launch_grid(B), B->block, B->stream) != hipSuccess) st = MLBM_E_HIP;
                 }
                 float ms = 0.0f;
                 if (hipEventRecord(B->ev1, B->stream) != hipSuccess || hipEventSynchronize(B->ev1) != hipSuccess ||
@@ -1046,7 +1066,7 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
     for (size_t i = 0; i < B->inst.size(); ++i) {
         if (!backup[i]) continue;
         Instance &I = B->inst[i];
-        const size_t bytes = sb * Q * (size_t)I.hd.N;
+        const size_t bytes = sb * storage_values(I.hd);
         if (hipMemcpyAsync(I.hd.f[parity_of(I)], backup[i], bytes, hipMemcpyDeviceToDevice, B->stream) != hipSuccess)
             st = MLBM_E_HIP;
         if (I.hd.ctr && hipMemcpyAsync(I.hd.ctr, ctr_backup.data() + 2 * i, 2 * sizeof(uint32_t), hipMemcpyHostToDevice,
@@ -1071,7 +1091,7 @@ mlbm_status mlbm_batch_autotune(mlbm_batch b, int steps, int *best_block, int *b
 
 // ---------------- checkpoints ---------------------------------------------
 
-static const char CK_MAGIC[8] = {'M', 'L', 'B', 'M', 'C', 'K', '0', '5'};
+static const char CK_MAGIC[8] = {'M', 'L', 'B', 'M', 'C', 'K', '0', '6'};
 
 mlbm_status mlbm_save(mlbm_handle h, const char *path)
 {
@@ -1079,7 +1099,7 @@ mlbm_status mlbm_save(mlbm_handle h, const char *path)
     if (!I || !path) return fail(MLBM_E_ARG, "null argument");
     Batch *B = h->b;
     const size_t N = (size_t)I->hd.N, sb = storage_bytes(B->st);
-    std::vector<char> pops(sb * Q * N);
+    std::vector<char> pops(sb * storage_values(I->hd));   // storage layout, padding included
     std::vector<double> us(3 * N);
     std::vector<float> ref(I->hd.ref ? (size_t)Q * I->hd.n1 : 0);
     std::vector<WindowState> ws;
@@ -1128,7 +1148,7 @@ mlbm_status mlbm_load(const char *path, void *hip_stream, mlbm_handle *out)
         return fail(MLBM_E_IO, "checkpoint description invalid: " + g_err);
     }
     const size_t N = (size_t)d.n1 * d.n2 * d.n3, sb = storage_bytes(d.precision);
-    std::vector<char> pops(sb * Q * N);
+    std::vector<char> pops(sb * (size_t)Q * d.n1 * d.n2 * x3_pitch(d.n3));
     std::vector<double> us(3 * N);
     std::vector<float> ref(uses_ref(d.precision) ? (size_t)Q * d.n1 : 0);
     uint32_t ctr = 0;

@@ -172,14 +172,14 @@ __global__ void init_kernel(const InstDesc *dd, const double *init_u, int parity
     const InstDesc &d = *dd;
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= d.N) return;
-    const int x1 = n / d.P, col = n - x1 * d.P;
+    const int x1 = n / d.P, col = storage_col(d, n - x1 * d.P);
     double g[Q];
     init_offsets(d, n, init_u, g);
     using T = typename Codec<ST>::T;
     T *dst = (T *)d.f[parity];
     for (int q = 0; q < Q; ++q) {
         const double r = Codec<ST>::REF ? (double)d.ref[x1 * Q + q] : 0.0;
-        dst[pop_elem(q, x1, col, d.P)] = Codec<ST>::from_f64(g[q], wq(q), r);
+        dst[pop_elem(q, x1, col, d.Pp)] = Codec<ST>::from_f64(g[q], wq(q), r);
     }
 }
 
@@ -205,10 +205,11 @@ __global__ void reref_kernel(const InstDesc *dd, int parity, float *ref)
     const InstDesc &d = *dd;
     const int x1 = blockIdx.x, q = blockIdx.y;
     __shared__ double part[256];
-    T *plane = (T *)d.f[parity] + ((size_t)x1 * Q + q) * d.P;
+    T *plane = (T *)d.f[parity] + ((size_t)x1 * Q + q) * d.Pp;
     const float r_old = ref[x1 * Q + q];
     double acc = 0.0;
-    for (int col = threadIdx.x; col < d.P; col += blockDim.x) acc += (double)Codec<ST>::decode(plane[col], r_old);
+    for (int col = threadIdx.x; col < d.P; col += blockDim.x)
+        acc += (double)Codec<ST>::decode(plane[storage_col(d, col)], r_old);
     part[threadIdx.x] = acc;
     __syncthreads();
     for (int h = blockDim.x / 2; h > 0; h >>= 1) {
@@ -219,7 +220,8 @@ __global__ void reref_kernel(const InstDesc *dd, int parity, float *ref)
     const uint32_t key = mix32(d.salt ^ 0x2545F491u) + d.ctr[parity] * 0x85EBCA77u + (uint32_t)q * 0xC2B2AE3Du;
     for (int col = threadIdx.x; col < d.P; col += blockDim.x) {
         const uint32_t bits = mix32(key + (uint32_t)(x1 * d.P + col) * 0x9E3779B9u);
-        plane[col] = Codec<ST>::encode_sr(Codec<ST>::decode(plane[col], r_old), r_new, bits);
+        T &v = plane[storage_col(d, col)];
+        v = Codec<ST>::encode_sr(Codec<ST>::decode(v, r_old), r_new, bits);
     }
     if (threadIdx.x == 0) ref[x1 * Q + q] = r_new;   // this workgroup is its only reader
 }
@@ -304,7 +306,7 @@ __device__ __forceinline__ void pull_f64(const InstDesc &d, int parity, int x1, 
         const int col = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip, row);
         const int qs = flip ? qo : (int)q;
         const double r = Codec<ST>::REF ? (double)d.ref[row * Q + qs] : 0.0;
-        g[q] = Codec<ST>::to_f64(gload<T>(src, sizeof(T) * pop_elem(qs, row, col, d.P)), wq(q), r);
+        g[q] = Codec<ST>::to_f64(gload<T>(src, sizeof(T) * pop_elem(qs, row, col, d.Pp)), wq(q), r);
     });
 }
 
@@ -449,10 +451,10 @@ __global__ void decode_kernel(InstDesc d, int parity, double *f)
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)Q * d.N) return;
     const int q = (int)(i / d.N);
-    const int n = (int)(i - (size_t)q * d.N), x1 = n / d.P;
+    const int n = (int)(i - (size_t)q * d.N), x1 = n / d.P, col = storage_col(d, n - x1 * d.P);
     const double w = wq(q);
     const double r = Codec<ST>::REF ? (double)d.ref[x1 * Q + q] : 0.0;
-    f[i] = Codec<ST>::to_f64(((const T *)d.f[parity])[pop_elem(q, x1, n - x1 * d.P, d.P)], w, r) + w;
+    f[i] = Codec<ST>::to_f64(((const T *)d.f[parity])[pop_elem(q, x1, col, d.Pp)], w, r) + w;
 }
 
 template <int ST>
@@ -462,10 +464,10 @@ __global__ void encode_kernel(InstDesc d, int parity, const double *f)
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (size_t)Q * d.N) return;
     const int q = (int)(i / d.N);
-    const int n = (int)(i - (size_t)q * d.N), x1 = n / d.P;
+    const int n = (int)(i - (size_t)q * d.N), x1 = n / d.P, col = storage_col(d, n - x1 * d.P);
     const double w = wq(q);
     const double r = Codec<ST>::REF ? (double)d.ref[x1 * Q + q] : 0.0;
-    ((T *)d.f[parity])[pop_elem(q, x1, n - x1 * d.P, d.P)] = Codec<ST>::from_f64(f[i] - w, w, r);
+    ((T *)d.f[parity])[pop_elem(q, x1, col, d.Pp)] = Codec<ST>::from_f64(f[i] - w, w, r);
 }
 
 hipError_t launch_decode(const InstDesc &h, int st, int parity, double *f, hipStream_t s)

@@ -2,8 +2,11 @@
 //
 // HBM layout of one instance:
 //   populations  two buffers (pull: read one, write the other), each
-//                [n1][41][n2][n3] of the storage type (the 41 planes of an
-//                x1 row together), x3 fastest.  Stored
+//                [n1][41][n2][n3p] of the storage type (the 41 planes of an
+//                x1 row together), x3 fastest, with the x3 pitch n3p = n3
+//                rounded up to 16 values so that every x2 row of every plane
+//                starts on a 64-byte boundary (odd n3 cost a third of the
+//                step kernel's throughput); the padding is never read.  Stored
 //                values are offsets from the lattice weights: g = f - w_q
 //                for FP64/FP32, d = f / w_q - 1 - r for FP16/BF16 (r: the
 //                row's reference offset of the population).
@@ -50,10 +53,11 @@ struct InstDesc {
     uint32_t salt;         // per-instance key of the stochastic rounding
     int n1, n2, n3, walls;
     int eqwall;            // 1: the x1 walls are equilibrium walls (wall-node rows 0 and n1 - 1)
-    int P, N;              // n2*n3, n1*n2*n3
+    int P, N;              // n2*n3, n1*n2*n3 (node count; node n = (x1*n2 + x2)*n3 + x3)
+    int n3p, Pp;           // storage pitch of x3 (n3 rounded up to 16) and of a plane (n2*n3p)
     int n3g;               // 1 or n3
-    int tpr;               // tiles per x1 row
-    uint64_t n3_magic;     // ceil(2^40 / n3): col / n3 = (col * magic) >> 40
+    int tpr;               // tiles per x1 row (over the Pp storage columns)
+    uint64_t n3_magic;     // ceil(2^40 / n3p): col / n3p = (col * magic) >> 40 for storage columns
     double omega;          // 1 / tau
     double kappa;          // 1 - 1/(2 tau) (improved forcing) or 0 (old)
     double force;          // covariant body force K

@@ -410,13 +410,21 @@ constexpr int CVALS[5] = {-3, -1, 0, 1, 3};
 // Per-lane byte offsets of the pull sources inside an x1 row: o2[s] for the
 // theta shift -CVALS[s] (always periodic), o3[s] for the x3 shift.
 // Storage order of an instance's populations: x1 rows outermost, then the
-// 41 population planes of that row (P = n2*n3 values each, x3 fastest).
-// Element (q, x1, col) sits at (x1*Q + q)*P + col, so the 41 read and the
-// 41 write streams of a tile each lie within one block of 41*P values; with
+// 41 population planes of that row (Pp = n2*n3p values each, x3 fastest
+// with the padded pitch n3p). Element (q, x1, col) with the storage column
+// col = x2*n3p + x3 sits at (x1*Q + q)*Pp + col, so the 41 read and the 41
+// write streams of a tile each lie within one block of 41*Pp values; with
 // planes N values apart the same streams cost about 15 % more HBM time.
-__host__ __device__ __forceinline__ uint64_t pop_elem(int q, int x1, int col, int P)
+__host__ __device__ __forceinline__ uint64_t pop_elem(int q, int x1, int col, int Pp)
 {
-    return ((uint64_t)x1 * Q + (uint64_t)q) * (uint64_t)P + (uint64_t)col;
+    return ((uint64_t)x1 * Q + (uint64_t)q) * (uint64_t)Pp + (uint64_t)col;
+}
+
+// Storage column of node n (x1 row, in-row node index x2*n3 + x3).
+__host__ __device__ __forceinline__ int storage_col(const InstDesc &d, int in_row)
+{
+    const int x2 = in_row / d.n3;
+    return x2 * d.n3p + (in_row - x2 * d.n3);
 }
 
 // Random seeds of the stochastic rounding of node n's 41 populations in the
@@ -463,11 +471,11 @@ struct RefRow {
 
 struct LaneOffsets {
     uint32_t o2[5], o3[5];
-    __device__ __forceinline__ void init(int x2, int x3, int n2, int n3, bool per3, uint32_t S)
+    __device__ __forceinline__ void init(int x2, int x3, int n2, int n3, int n3p, bool per3, uint32_t S)
     {
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
-            o2[s] = (uint32_t)(wrap_axis(x2 - CVALS[s], n2) * n3) * S;
+            o2[s] = (uint32_t)(wrap_axis(x2 - CVALS[s], n2) * n3p) * S;
             o3[s] = (uint32_t)(per3 ? wrap_axis(x3 - CVALS[s], n3) : x3 - CVALS[s]) * S;
         }
     }
@@ -475,7 +483,7 @@ struct LaneOffsets {
 
 // Pull from x - c inside the domain (no wall within reach): the row x1 - c1
 // is uniform across the wavefront, only the in-row byte offset is per lane.
-template <int ST, class R>
+template <int ST, bool EQW = false, class R>
 __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, int x1, const LaneOffsets &L,
                                             const R &ref, typename Codec<ST>::G (&g)[Q])
 {
@@ -483,7 +491,7 @@ __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, 
     using C = typename Codec<ST>::C;
     constexpr uint64_t S = sizeof(T);
     const bool per1 = !(d.walls & 1);
-    const uint64_t PS = (uint64_t)d.P * S;
+    const uint64_t PS = (uint64_t)d.Pp * S;
     int rows[5];      // source row x1 - CVALS[s]
     uint64_t rb[5];   // byte offset of plane 0 of that row
 #pragma unroll
@@ -492,7 +500,7 @@ __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, 
         if (per1) r1 = wrap_axis(r1, d.n1);
         // equilibrium walls: the region beyond a wall node is at rest in the
         // wall node's state, so a pull from beyond it reads the wall node
-        if (d.eqwall) r1 = r1 < 0 ? 0 : (r1 > d.n1 - 1 ? d.n1 - 1 : r1);
+        if (EQW && d.eqwall) r1 = r1 < 0 ? 0 : (r1 > d.n1 - 1 ? d.n1 - 1 : r1);
         rows[k] = r1;
         rb[k] = (uint64_t)r1 * (uint64_t)Q * PS;
     }
@@ -522,7 +530,7 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
     using C = typename Codec<ST>::C;
     constexpr uint32_t S = sizeof(T);
     const bool per1 = !(d.walls & 1);
-    const uint32_t PS = (uint32_t)d.P * S;
+    const uint32_t PS = (uint32_t)d.Pp * S;
     int rows[7];      // source row x1 - t, t = -3..3
     uint32_t rb[7];   // byte offset of plane 0 of that row
 #pragma unroll
@@ -532,7 +540,7 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
         rows[k] = r1;
         rb[k] = (uint32_t)r1 * (uint32_t)Q * PS;
     }
-    const uint32_t n3S = (uint32_t)d.n3 * S;
+    const uint32_t n3S = (uint32_t)d.n3p * S;
     // in-row x2 offsets of x2 - t for t = -3..3
     const uint32_t o2t[7] = {L.o2[0], (uint32_t)wrap_axis(x2 + 2, d.n2) * n3S, L.o2[1], L.o2[2], L.o2[3],
                              (uint32_t)wrap_axis(x2 - 2, d.n2) * n3S, L.o2[4]};
@@ -586,8 +594,8 @@ __device__ __forceinline__ void gather_x1wall(const void *src, const InstDesc &d
     using C = typename Codec<ST>::C;
     constexpr uint32_t S = sizeof(T);
     const bool per3 = !(d.walls & 4);
-    const uint32_t PS = (uint32_t)d.P * S;
-    const uint32_t n3S = (uint32_t)d.n3 * S;
+    const uint32_t PS = (uint32_t)d.Pp * S;
+    const uint32_t n3S = (uint32_t)d.n3p * S;
     // in-row offsets of x - t along x2 and x3 for t = -2, 0, 2 (index 0, 1, 2)
     const uint32_t o2s[3] = {(uint32_t)wrap_axis(x2 + 2, d.n2) * n3S, L.o2[2], (uint32_t)wrap_axis(x2 - 2, d.n2) * n3S};
     const uint32_t o3s[3] = {(uint32_t)(per3 ? wrap_axis(x3 + 2, d.n3) : x3 + 2) * S, L.o3[2],
@@ -630,7 +638,8 @@ __device__ __forceinline__ void gather_x1wall(const void *src, const InstDesc &d
 // The backward trajectory from x along -c runs inside [-front, back]; it is
 // unfolded to y = front + 2m and folded back into [0, L], L = back + front:
 // crossings n_c = floor(y / L), every crossing reverses the velocity.
-// Returns the source column x2*n3 + x3 within the source row (written to row).
+// Returns the source storage column x2*n3p + x3 within the source row
+// (written to row).
 template <int C1, int C2, int C3>
 __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, int x2, int x3, bool &flip,
                                                     int &row)
@@ -640,14 +649,14 @@ __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, i
     flip = false;
     if constexpr (m == 0) {
         row = x1;
-        return x2 * d.n3 + x3;
+        return x2 * d.n3p + x3;
     } else {
         constexpr int h1 = C1 / m, h2 = C2 / m, h3 = C3 / m;
         if (d.eqwall) {   // wall nodes on axis 1 (clamped pull), x3 periodic
             int s1 = x1 - C1;
             s1 = s1 < 0 ? 0 : (s1 > d.n1 - 1 ? d.n1 - 1 : s1);
             row = s1;
-            return wrap_axis(x2 - C2, d.n2) * d.n3 + wrap_axis(x3 - C3, d.n3);
+            return wrap_axis(x2 - C2, d.n2) * d.n3p + wrap_axis(x3 - C3, d.n3);
         }
         int back = 1 << 28, front = 1 << 28;
         if constexpr (C1 != 0) {
@@ -681,7 +690,7 @@ __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, i
         s2 = wrap_axis(s2, d.n2);
         if (!(d.walls & 4)) s3 = wrap_axis(s3, d.n3);
         row = s1;
-        return s2 * d.n3 + s3;
+        return s2 * d.n3p + s3;
     }
 }
 
@@ -699,7 +708,7 @@ __device__ __forceinline__ void gather_general(const void *src, const InstDesc &
         int row;
         const int col = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip, row);
         const uint32_t qs = flip ? (uint32_t)qo : (uint32_t)q;
-        const uint32_t e = ((uint32_t)row * (uint32_t)Q + qs) * (uint32_t)d.P + (uint32_t)col;
+        const uint32_t e = ((uint32_t)row * (uint32_t)Q + qs) * (uint32_t)d.Pp + (uint32_t)col;
         C r = C(0);
         if constexpr (Codec<ST>::REF) r = (C)RefRow{d.ref}.get_r(0, row, (int)qs);   // per-lane row
         g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)(e * S)), r);

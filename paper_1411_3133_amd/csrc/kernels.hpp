@@ -15,7 +15,10 @@ struct StepArgs {
     int parity;              // read f[parity], write f[parity ^ 1]
 };
 
-hipError_t launch_step(const StepArgs &a, int pat, int st, bool check, int grid, int block, hipStream_t s);
+hipError_t launch_step(const StepArgs &a, int pat, int st, bool check, bool eqw, int grid, int block, hipStream_t s);
+// the two compiled variants (eqw: with the equilibrium-wall rows)
+hipError_t launch_step_plain(const StepArgs &a, int pat, int st, bool check, int grid, int block, hipStream_t s);
+hipError_t launch_step_eq(const StepArgs &a, int pat, int st, bool check, int grid, int block, hipStream_t s);
 
 // geometry of one instance (FP64, on the device)
 struct GeoParams {
