@@ -99,7 +99,26 @@ enum { MLBM_FORCING_IMPROVED = 0, MLBM_FORCING_OLD = 1 };
  *  tau           BGK relaxation parameter, > 0.5.
  *  force         covariant streamwise body force K (physical units); the
  *                contravariant force is g^{i theta} K.
- *  init_u        NULL for rest, else 3 N doubles [3][N] (host, copied). */
+ *  init_u        NULL for rest, else the initial physical contravariant
+ *                velocity (host, copied): 3 N doubles [3][N], or with
+ *                init_u_xsec = 1 3 n1 n3 doubles [3][n1][n3] used in every
+ *                theta slab.
+ *  target_De     > 0: the body force is derived from this Dean number (Sec.
+ *                III, Eq. (8)) through the closed-form laminar profile of a
+ *                constant covariant force, v = A r ln r + B r + C / r with
+ *                A = -K / (2 nu), nu = (tau - 1/2) cs2 Dt, on the channel of
+ *                streamwise radius R (cylinder r_i, ellipsoid r_i b^2, whose
+ *                force is then divided by b); flat: plane Poiseuille at
+ *                Reynolds number De.  `force` must be 0.  0: use `force`.
+ *  perturb_amp   > 0: start from that closed-form laminar profile (the mean
+ *                speed U_nom of target_De, or 1 without it) plus
+ *                perturb_amp U_nom xi of physical speed per cross-section
+ *                node and component, xi in [-1, 1) from SplitMix64 (Steele,
+ *                Lea & Flood 2014) keyed by `seed` (xi_i = (z_i >> 11)
+ *                2^-52 - 1, z_i = splitmix64(i ^ (seed * 0x100000001B3)),
+ *                i = (component n1 + x1) n3 + x3); init_u must be NULL.
+ *  seed          key of the start perturbation.
+ *  init_u_xsec   layout of init_u, see above. */
 typedef struct {
     int32_t kind;
     int32_t n1, n2, n3;
@@ -113,6 +132,11 @@ typedef struct {
     double tau;
     double force;
     const double *init_u;
+    double target_De;
+    double perturb_amp;
+    uint64_t seed;
+    int32_t init_u_xsec;
+    int32_t reserved;        /* 0 */
 } mlbm_desc;
 
 typedef struct mlbm_sim_s *mlbm_handle;
@@ -171,6 +195,13 @@ mlbm_status mlbm_run_until(mlbm_handle h, double tol, int64_t max_steps, int64_t
 mlbm_status mlbm_get_populations(mlbm_handle h, double *f);
 /* Overwrite the current state (encoded into the storage precision). */
 mlbm_status mlbm_set_populations(mlbm_handle h, const double *f);
+
+/* The same two operations on a caller-owned device buffer f [41][N] (FP64,
+ * absolute populations; e.g. a torch tensor's data pointer): get = 1
+ * decodes the current state into it, get = 0 encodes it into the current
+ * state.  Runs on the handle's stream and waits for it.  Errors: E_ARG,
+ * E_HIP. */
+mlbm_status mlbm_populations_device(mlbm_handle h, double *f, int get);
 
 /* One step of the nodes listed, from the current state, without advancing:
  * out[k][41] = f* at node nodes[k] (host arrays), rounded through the
@@ -295,6 +326,14 @@ mlbm_status mlbm_net_train(mlbm_net net, int64_t steps, int64_t batch, double lr
 
 /* Loss over the whole training set. */
 mlbm_status mlbm_net_dataset_loss(mlbm_net net, double *loss);
+
+/* Parameters of a trained network to a file (its shape, then the
+ * parameters in the order above as doubles), and a network created from
+ * such a file on `hip_stream` (NULL: a stream of its own).  The Adam
+ * moments are not kept.  Errors: E_ARG, E_IO (missing, truncated or of an
+ * unsupported shape), E_OOM, E_HIP. */
+mlbm_status mlbm_warmstart_save(mlbm_net net, const char *path);
+mlbm_status mlbm_warmstart_load(const char *path, void *hip_stream, mlbm_net *out);
 
 /* Predicted velocity field of a case, physical contravariant [3][N] (every
  * theta slab), ready to pass as mlbm_desc.init_u; host or device buffer. */

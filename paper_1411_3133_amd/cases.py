@@ -289,12 +289,15 @@ def cylinder_sweep(precision: str = "f32", De_values=None) -> List[Case]:
                           label=f"cyl64-De{De:g}") for De in De_values]
 
 
-def ellipsoid_96x192_cases(precision: str = "f16", De: float = 60.0) -> List[Case]:
-    """Double-curved channel: 96 x 4 x 192, R1/d = 20, R2/d in {5, 10, 20, 40}."""
+def ellipsoid_96x192_cases(precision: str = "f16", De: float = 60.0, n2: int = 4) -> List[Case]:
+    """Double-curved channel: 96 x n2 x 192, R1/d = 20, R2/d in {5, 10, 20, 40};
+    tau from the Mach rule at De = 150 (0.5708), raised to the measured
+    stability floor where that lies higher (R2/d = 5: 0.6668, 10: 0.5834),
+    at the price of Mach 0.3 being reached at a lower De there."""
     out = []
     for R2 in (5.0, 10.0, 20.0, 40.0):
-        tau = round(tau_for_mach(96, 150.0, 1.0, 20.0), 4)
-        out.append(ellipsoid_case(20.0, R2, 96, 4, 192, tau, De=De, precision=precision,
+        tau = max(round(tau_for_mach(96, 150.0, 1.0, 20.0), 4), math.ceil(stability_floor_tau(R2, 96) * 1e4) / 1e4)
+        out.append(ellipsoid_case(20.0, R2, 96, n2, 192, tau, De=De, precision=precision,
                                   label=f"ell96-R2_{R2:g}"))
     return out
 

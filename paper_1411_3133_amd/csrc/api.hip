@@ -183,6 +183,12 @@ mlbm_status validate(const mlbm_desc &d)
     if (!(d.tau > 0.5)) return fail(MLBM_E_ARG, "tau must be > 0.5");
     if (!(d.width > 0.0)) return fail(MLBM_E_ARG, "width must be > 0");
     if (!std::isfinite(d.force)) return fail(MLBM_E_ARG, "force must be finite");
+    if (!(d.target_De >= 0.0) || !std::isfinite(d.target_De)) return fail(MLBM_E_ARG, "target_De must be >= 0");
+    if (d.target_De > 0.0 && d.force != 0.0) return fail(MLBM_E_ARG, "give either force or target_De, not both");
+    if (!(d.perturb_amp >= 0.0) || !std::isfinite(d.perturb_amp)) return fail(MLBM_E_ARG, "perturb_amp must be >= 0");
+    if (d.perturb_amp > 0.0 && d.init_u) return fail(MLBM_E_ARG, "perturb_amp builds the start: init_u must be NULL");
+    if (d.init_u_xsec != 0 && d.init_u_xsec != 1) return fail(MLBM_E_ARG, "init_u_xsec must be 0 or 1");
+    if (d.reserved != 0) return fail(MLBM_E_ARG, "reserved must be 0");
     if (d.kind != MLBM_FLAT && !(d.r_inner > 0.0)) return fail(MLBM_E_ARG, "r_inner must be > 0");
     if (d.kind == MLBM_ELLIPSOID) {
         if (!(d.b > 0.0)) return fail(MLBM_E_ARG, "b must be > 0");
@@ -204,6 +210,114 @@ void scales(const mlbm_desc &d, double &dt, double s[3])
         s[1] = 1.0 / (d.b * d.r_inner);
         s[2] = 1.0 / d.r_inner;
     }
+}
+
+// ---- case set-up: body force from a Dean number, closed-form start ---------
+
+double lattice_dt(const mlbm_desc &d) { return d.width / (eq_walls(d) ? d.n1 - 1 : d.n1); }
+double nu_phys(const mlbm_desc &d) { return (d.tau - 0.5) * CS2 * lattice_dt(d); }
+
+// (A, B, C) of v(r) = A r ln r + B r + C / r with v(r_i) = v(r_o) = 0: the
+// azimuthal balance nu (d/dr)((1/r) d(r v)/dr) = -K / r of a constant
+// covariant force K (Sec. III), A = -K / (2 nu).
+void curved_coeffs(double ri, double ro, double K, double nu, double &A, double &B, double &C)
+{
+    A = -K / (2.0 * nu);
+    const double b0 = -A * ri * std::log(ri), b1 = -A * ro * std::log(ro);
+    const double det = ri / ro - ro / ri;          // | ri 1/ri ; ro 1/ro |
+    B = (b0 / ro - b1 / ri) / det;
+    C = (ri * b1 - ro * b0) / det;
+}
+
+double curved_v(double r, double ri, double ro, double K, double nu)
+{
+    double A, B, C;
+    curved_coeffs(ri, ro, K, nu, A, B, C);
+    return A * r * std::log(r) + B * r + C / r;
+}
+
+// (1/d) int_{r_i}^{r_o} v dr
+double curved_mean(double ri, double ro, double K, double nu)
+{
+    double A, B, C;
+    curved_coeffs(ri, ro, K, nu, A, B, C);
+    auto prim = [&](double r) { return A * (0.5 * r * r * std::log(r) - 0.25 * r * r) + 0.5 * B * r * r + C * std::log(r); };
+    return (prim(ro) - prim(ri)) / (ro - ri);
+}
+
+double stream_radius(const mlbm_desc &d) { return d.kind == MLBM_CYLINDER ? d.r_inner : d.r_inner * d.b * d.b; }
+
+// Mean streamwise speed implied by De (Eq. (8)): De nu / d (flat: the
+// Reynolds number), over sqrt(d / R) for curved channels.
+double nominal_velocity(const mlbm_desc &d, double De)
+{
+    const double v = De * nu_phys(d) / d.width;
+    return d.kind == MLBM_FLAT ? v : v / std::sqrt(d.width / stream_radius(d));
+}
+
+// Covariant force giving De for the laminar closed-form flow; the ellipsoid
+// uses the channel of its streamwise radius R = r_i b^2 with the physical
+// force matched at the inner wall (K / b).
+double nominal_force(const mlbm_desc &d, double De)
+{
+    const double nu = nu_phys(d), w = d.width;
+    if (d.kind == MLBM_FLAT) return 12.0 * nu * nominal_velocity(d, De) / (w * w);
+    const double R = stream_radius(d);
+    const double K = nominal_velocity(d, De) / curved_mean(R, R + w, 1.0, nu);
+    return d.kind == MLBM_CYLINDER ? K : K / d.b;
+}
+
+uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Closed-form start: laminar streamwise profile plus the seeded
+// perturbation, physical contravariant [3][n1][n2][n3].
+std::vector<double> closed_form_start(const mlbm_desc &d, double force)
+{
+    const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
+    const size_t N = (size_t)n1 * n2 * n3;
+    const double dt = lattice_dt(d), nu = nu_phys(d), w = d.width;
+    const double o1 = eq_walls(d) ? 0.0 : 0.5;
+    const double Unom = d.target_De > 0.0 ? nominal_velocity(d, d.target_De) : 1.0;
+    const uint64_t key = d.seed * 0x100000001B3ull;
+    std::vector<double> u(3 * N, 0.0);
+    for (int x1 = 0; x1 < n1; ++x1) {
+        const double y = (x1 + o1) * dt;
+        const double r = d.kind == MLBM_FLAT ? y : d.r_inner + y;
+        for (int x3 = 0; x3 < n3; ++x3) {
+            const double ph = (x3 + 0.5 - 0.5 * n3) * dt / d.r_inner;
+            double lam = 0.0, sc1 = 1.0, sc2 = 1.0;
+            if (d.kind == MLBM_FLAT) {
+                lam = force / (2.0 * nu) * y * (w - y);
+            } else if (d.kind == MLBM_CYLINDER) {
+                lam = curved_v(r, d.r_inner, d.r_inner + w, force, nu) / r;
+                sc1 = 1.0 / r;
+            } else {
+                const double R = stream_radius(d), cp = std::cos(ph);
+                lam = curved_v(R + y, R, R + w, force * d.b, nu) / (r * d.b * cp);
+                sc1 = 1.0 / (r * d.b * cp);
+                sc2 = 1.0 / r;
+            }
+            double xi[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < 3; ++c) {
+                const uint64_t i = ((uint64_t)c * n1 + x1) * n3 + x3;
+                xi[c] = (double)(splitmix64(i ^ key) >> 11) * 0x1p-52 - 1.0;
+            }
+            const double amp = d.perturb_amp * Unom;
+            for (int x2 = 0; x2 < n2; ++x2) {
+                const size_t n = ((size_t)x1 * n2 + x2) * n3 + x3;
+                u[n] = amp * xi[0];
+                u[N + n] = lam + amp * xi[1] * sc1;
+                u[2 * N + n] = amp * xi[2] * sc2;
+            }
+        }
+    }
+    return u;
 }
 
 mlbm_status ensure_scratch(Batch *B, size_t bytes)
@@ -554,7 +668,13 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
         h.n3_magic = ((1ull << 40) + (uint64_t)h.n3p - 1) / (uint64_t)h.n3p;
         h.omega = 1.0 / d.tau;
         h.kappa = d.forcing_mode == MLBM_FORCING_IMPROVED ? 1.0 - 1.0 / (2.0 * d.tau) : 0.0;
-        h.force = d.force;
+        // the retained description carries the resolved force and no start
+        // recipe (a checkpoint restores the state itself)
+        if (d.target_De > 0.0) I.desc.force = nominal_force(d, d.target_De);
+        I.desc.target_De = 0.0;
+        I.desc.perturb_amp = 0.0;
+        I.desc.init_u_xsec = 0;
+        h.force = I.desc.force;
         scales(d, I.dt, h.s);
         const size_t fb = sbytes * storage_values(h);
         if (hipMalloc(&h.f[0], fb) != hipSuccess || hipMalloc(&h.f[1], fb) != hipSuccess ||
@@ -566,7 +686,7 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
             return bail(fail(MLBM_E_HIP, "hipMemsetAsync failed"));
         h.ref = nullptr;
         h.ctr = nullptr;
-        h.salt = desc_salt(d);
+        h.salt = desc_salt(I.desc);
         if (uses_ref(B->st)) {
             float *ref = nullptr;
             if (hipMalloc(&ref, sizeof(float) * Q * (size_t)h.n1) != hipSuccess)
@@ -583,10 +703,26 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
     for (int i = 0; i < n; ++i) {
         Instance &I = B->inst[i];
         double *du = nullptr;
-        if (ds[i].init_u) {
+        std::vector<double> field;     // host start field [3][N], when built here
+        const double *src = ds[i].init_u;
+        if (ds[i].perturb_amp > 0.0) {
+            field = closed_form_start(ds[i], I.desc.force);
+            src = field.data();
+        } else if (src && ds[i].init_u_xsec) {   // the cross section repeated in every theta slab
+            const int n1 = I.hd.n1, n2 = I.hd.n2, n3 = I.hd.n3;
+            field.resize(3 * (size_t)I.hd.N);
+            for (int c = 0; c < 3; ++c)
+                for (int x1 = 0; x1 < n1; ++x1)
+                    for (int x2 = 0; x2 < n2; ++x2)
+                        for (int x3 = 0; x3 < n3; ++x3)
+                            field[(size_t)c * I.hd.N + ((size_t)x1 * n2 + x2) * n3 + x3] =
+                                src[((size_t)c * n1 + x1) * n3 + x3];
+            src = field.data();
+        }
+        if (src) {
             const size_t bytes = sizeof(double) * 3 * (size_t)I.hd.N;
             if (hipMalloc(&du, bytes) != hipSuccess) return bail(fail(MLBM_E_OOM, "init_u staging failed"));
-            if (hipMemcpyAsync(du, ds[i].init_u, bytes, hipMemcpyHostToDevice, B->stream) != hipSuccess) {
+            if (hipMemcpyAsync(du, src, bytes, hipMemcpyHostToDevice, B->stream) != hipSuccess) {
                 (void)hipFree(du);
                 return bail(fail(MLBM_E_HIP, "init_u upload failed"));
             }
@@ -873,6 +1009,17 @@ mlbm_status mlbm_set_populations(mlbm_handle h, const double *f)
     if (s != MLBM_OK) return s;
     HIP_TRY(hipMemcpyAsync(B->d_scratch, f, bytes, hipMemcpyHostToDevice, B->stream));
     HIP_TRY(launch_encode(I->hd, B->st, parity_of(*I), B->d_scratch, B->stream));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    return MLBM_OK;
+}
+
+mlbm_status mlbm_populations_device(mlbm_handle h, double *f, int get)
+{
+    Instance *I = inst_of(h);
+    if (!I || !f) return fail(MLBM_E_ARG, "null argument");
+    Batch *B = h->b;
+    if (get) HIP_TRY(launch_decode(I->hd, B->st, parity_of(*I), f, B->stream));
+    else HIP_TRY(launch_encode(I->hd, B->st, parity_of(*I), f, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));
     return MLBM_OK;
 }

@@ -263,15 +263,17 @@ __global__ void adam_kernel(float *p, const float *g, float *m, float *v, long n
 // ---- features, targets and predictions of a case ------------------------
 
 struct CaseGeo {
-    int kind, n1, n2, n3;
+    int kind, n1, n2, n3, eqwall;
     double r_inner, width, b, s2, s3;
     double f0, f1, f2;   // De/100, R1/d/20, ln(R2/R1)/ln 4
 };
 
 __device__ void node_geo(const CaseGeo &c, int x1, int x3, double &sq2, double &sq3, double &arc)
 {
-    const double dt = c.width / c.n1;
-    const double r = c.kind == MLBM_FLAT ? (x1 + 0.5) * dt : c.r_inner + (x1 + 0.5) * dt;
+    // node placement of the solver: cell centred, or wall nodes at both ends
+    const double dt = c.width / (c.eqwall ? c.n1 - 1 : c.n1);
+    const double o1 = c.eqwall ? 0.0 : 0.5;
+    const double r = c.kind == MLBM_FLAT ? (x1 + o1) * dt : c.r_inner + (x1 + o1) * dt;
     sq2 = 1.0; sq3 = 1.0;
     if (c.kind == MLBM_ELLIPSOID) {
         const double ph = (x3 + 0.5 - 0.5 * c.n3) * dt * c.s3;
@@ -339,6 +341,7 @@ CaseGeo case_geo(const mlbm_desc &d, double De, double R1_d, double R2_d)
 {
     CaseGeo c{};
     c.kind = d.kind; c.n1 = d.n1; c.n2 = d.n2; c.n3 = d.n3;
+    c.eqwall = (d.walls & MLBM_WALL_EQUILIBRIUM) ? 1 : 0;
     c.r_inner = d.r_inner; c.width = d.width; c.b = d.b;
     c.s2 = d.kind == MLBM_ELLIPSOID ? 1.0 / (d.b * d.r_inner) : 1.0;
     c.s3 = d.kind == MLBM_ELLIPSOID ? 1.0 / d.r_inner : 1.0;
@@ -627,6 +630,45 @@ mlbm_status mlbm_net_dataset_loss(mlbm_net N, double *loss)
 {
     if (!N || !loss || N->M <= 0) return nfail(MLBM_E_ARG, "empty dataset");
     return run_gradient(N, N->X, N->T, N->M, N->M, 0, loss);
+}
+
+static const char NET_MAGIC[8] = {'M', 'L', 'B', 'M', 'N', 'E', 'T', '1'};
+
+mlbm_status mlbm_warmstart_save(mlbm_net N, const char *path)
+{
+    if (!N || !path) return nfail(MLBM_E_ARG, "null argument");
+    const int64_t np = N->sh.np;
+    std::vector<double> p(np);
+    mlbm_status st = mlbm_net_params(N, p.data(), 1);
+    if (st != MLBM_OK) return st;
+    FILE *fp = fopen(path, "wb");
+    if (!fp) return nfail(MLBM_E_IO, std::string("cannot open ") + path);
+    const int32_t hd[2] = {N->sh.H, N->sh.depth};
+    bool ok = fwrite(NET_MAGIC, 1, 8, fp) == 8 && fwrite(hd, sizeof(hd), 1, fp) == 1 && fwrite(&np, sizeof(np), 1, fp) == 1 &&
+              fwrite(p.data(), sizeof(double), (size_t)np, fp) == (size_t)np;
+    ok = (fclose(fp) == 0) && ok;
+    return ok ? MLBM_OK : nfail(MLBM_E_IO, std::string("write failed: ") + path);
+}
+
+mlbm_status mlbm_warmstart_load(const char *path, void *hip_stream, mlbm_net *out)
+{
+    if (!path || !out) return nfail(MLBM_E_ARG, "null argument");
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return nfail(MLBM_E_IO, std::string("cannot open ") + path);
+    char mg[8];
+    int32_t hd[2] = {0, 0};
+    int64_t np = 0;
+    bool ok = fread(mg, 1, 8, fp) == 8 && !memcmp(mg, NET_MAGIC, 8) && fread(hd, sizeof(hd), 1, fp) == 1 &&
+              fread(&np, sizeof(np), 1, fp) == 1;
+    if (!ok || mlbm_net_num_params(hd[0], hd[1]) != np) {
+        fclose(fp);
+        return nfail(MLBM_E_IO, "not a warm-start network file, or a shape this library does not support");
+    }
+    std::vector<double> p((size_t)np);
+    ok = fread(p.data(), sizeof(double), (size_t)np, fp) == (size_t)np;
+    fclose(fp);
+    if (!ok) return nfail(MLBM_E_IO, "network file truncated");
+    return mlbm_net_create(hd[0], hd[1], p.data(), hip_stream, out);
 }
 
 mlbm_status mlbm_warmstart_predict(mlbm_net N, const mlbm_desc *d, double De, double R1_d, double R2_d, double U_nom,

@@ -37,6 +37,8 @@ class Desc(C.Structure):
         ("r_inner", C.c_double), ("width", C.c_double), ("b", C.c_double),
         ("tau", C.c_double), ("force", C.c_double),
         ("init_u", C.POINTER(C.c_double)),
+        ("target_De", C.c_double), ("perturb_amp", C.c_double), ("seed", C.c_uint64),
+        ("init_u_xsec", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -51,7 +53,8 @@ EXPORTS = [
     "mlbm_net_num_params", "mlbm_net_create", "mlbm_net_destroy", "mlbm_net_last_error",
     "mlbm_net_params", "mlbm_net_forward", "mlbm_net_gradient", "mlbm_net_adam_step",
     "mlbm_net_dataset_add", "mlbm_net_dataset_clear", "mlbm_net_dataset_size", "mlbm_net_train",
-    "mlbm_net_dataset_loss", "mlbm_warmstart_predict",
+    "mlbm_net_dataset_loss", "mlbm_warmstart_predict", "mlbm_warmstart_save", "mlbm_warmstart_load",
+    "mlbm_populations_device",
 ]
 
 _lib = None
@@ -65,6 +68,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1411_3133_amd.build` "
                           "or __graft_entry__.build()")
+    # PyTorch ships its own HIP runtime. Importing it first makes the library
+    # bind to that same runtime, so torch tensors, streams and the library's
+    # buffers live in one runtime whatever the caller imports later.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
     L.mlbm_init_geometry.argtypes = [C.POINTER(Desc), vp, C.POINTER(vp)]
@@ -117,6 +127,9 @@ def load():
     L.mlbm_net_dataset_loss.argtypes = [vp, dp]
     L.mlbm_warmstart_predict.argtypes = [vp, C.POINTER(Desc), C.c_double, C.c_double, C.c_double, C.c_double,
                                          vp, C.c_int]
+    L.mlbm_warmstart_save.argtypes = [vp, C.c_char_p]
+    L.mlbm_warmstart_load.argtypes = [C.c_char_p, vp, C.POINTER(vp)]
+    L.mlbm_populations_device.argtypes = [vp, vp, C.c_int]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -137,17 +150,29 @@ def lattice():
     return c.reshape(Q, 3), w, cs2.value
 
 
-def make_desc(case: Case, init_u: Optional[np.ndarray] = None):
-    """Desc for a Case; returns (desc, keepalive)."""
+def make_desc(case: Case, init_u: Optional[np.ndarray] = None, start: Optional[dict] = None):
+    """Desc for a Case; returns (desc, keepalive).  init_u: 3 N values, or
+    3 n1 n3 values (one cross section, used in every theta slab).  start:
+    dict(target_De=..., perturb_amp=..., seed=...) lets the library derive
+    the force from the Dean number and build the closed-form perturbed
+    start itself (force is then passed as 0)."""
     keep = None
     d = Desc(kind=KIND[case.kind], n1=case.n1, n2=case.n2, n3=case.n3, walls=case.walls,
              forcing_mode=case.forcing_mode, precision=PRECISION[case.precision],
              check_every=case.check_every, r_inner=case.r_inner, width=case.width, b=case.b,
              tau=case.tau, force=case.force, init_u=None)
+    if start:
+        if start.get("target_De"):
+            d.target_De = float(start["target_De"])
+            d.force = 0.0
+        d.perturb_amp = float(start.get("perturb_amp", 0.0))
+        d.seed = int(start.get("seed", 0))
     if init_u is not None:
         keep = np.ascontiguousarray(init_u, np.float64).reshape(-1)
-        if keep.size != 3 * case.N:
-            raise ValueError("init_u must hold 3 * N values")
+        if keep.size == 3 * case.n1 * case.n3 and keep.size != 3 * case.N:
+            d.init_u_xsec = 1
+        elif keep.size != 3 * case.N:
+            raise ValueError("init_u must hold 3 N or 3 n1 n3 values")
         d.init_u = keep.ctypes.data_as(C.POINTER(C.c_double))
     return d, keep
 
@@ -173,7 +198,7 @@ class Sim:
     """One instance (owning handle) or a view into a Batch."""
 
     def __init__(self, case: Optional[Case] = None, init_u=None, stream=None, _handle=None, _owner=True,
-                 _batch=None):
+                 _batch=None, start: Optional[dict] = None):
         L = load()
         self.case = case
         self._owner = _owner
@@ -181,7 +206,7 @@ class Sim:
         if _handle is not None:
             self._h = _handle
         else:
-            d, keep = make_desc(case, init_u)
+            d, keep = make_desc(case, init_u, start)
             h = C.c_void_p()
             _check(L.mlbm_init_geometry(C.byref(d), _stream_arg(stream), C.byref(h)))
             self._h = h
@@ -248,6 +273,11 @@ class Sim:
     def set_f(self, f):
         f = np.ascontiguousarray(f, np.float64).reshape(-1)
         _check(load().mlbm_set_populations(self._h, f.ctypes.data_as(C.c_void_p)))
+
+    def populations_device(self, ptr: int, get: bool = True):
+        """Decode the state into (get) or encode it from a caller-owned device
+        buffer of 41 N doubles (e.g. a torch tensor's data_ptr())."""
+        _check(load().mlbm_populations_device(self._h, C.c_void_p(ptr), 1 if get else 0))
 
     def step_nodes(self, nodes):
         nodes = np.ascontiguousarray(nodes, np.int64)
@@ -421,6 +451,27 @@ class Net:
         loss = C.c_double()
         _net_check(load().mlbm_net_dataset_loss(self._h, C.byref(loss)))
         return loss.value
+
+    def save(self, path: str):
+        _net_check(load().mlbm_warmstart_save(self._h, path.encode()))
+
+    @classmethod
+    def load_file(cls, path: str, stream=None) -> "Net":
+        """A network created by the library from a file mlbm_warmstart_save wrote."""
+        import struct
+        with open(path, "rb") as f:
+            head = f.read(16)
+        if len(head) < 16 or head[:8] != b"MLBMNET1":
+            raise MlbmError(E_IO, f"{path} is not a warm-start network file")
+        hidden, depth = struct.unpack("<ii", head[8:16])
+        L = load()
+        h = C.c_void_p()
+        _net_check(L.mlbm_warmstart_load(path.encode(), _stream_arg(stream), C.byref(h)))
+        net = cls.__new__(cls)
+        net._h = h
+        net.hidden, net.depth = hidden, depth
+        net.np = int(L.mlbm_net_num_params(hidden, depth))
+        return net
 
     def predict(self, case: Case, De, R1_d, R2_d, U_nom):
         d, _ = make_desc(case)

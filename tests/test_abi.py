@@ -97,6 +97,30 @@ def test_invalid_descriptions_are_rejected_before_any_device_work(bad):
     assert mlbm.load().mlbm_last_error()
 
 
+@pytest.mark.parametrize("field,value", [
+    ("target_De", -1.0), ("target_De", float("nan")), ("perturb_amp", -0.1), ("init_u_xsec", 2), ("reserved", 1),
+])
+def test_invalid_start_recipes_are_rejected(field, value):
+    import ctypes as C
+    d, _ = mlbm.make_desc(K.laminar_cylinder())
+    setattr(d, field, value)
+    h = C.c_void_p()
+    assert mlbm.load().mlbm_init_geometry(C.byref(d), None, C.byref(h)) == mlbm.E_ARG
+    assert mlbm.load().mlbm_last_error()
+
+
+def test_target_dean_number_excludes_an_explicit_force():
+    import ctypes as C
+    d, _ = mlbm.make_desc(K.laminar_cylinder())      # carries its nominal force
+    d.target_De = 20.0
+    h = C.c_void_p()
+    assert mlbm.load().mlbm_init_geometry(C.byref(d), None, C.byref(h)) == mlbm.E_ARG
+    init = np.zeros(3 * K.laminar_cylinder().N)
+    d, keep = mlbm.make_desc(K.laminar_cylinder(), init)
+    d.perturb_amp = 1e-3                              # the library builds the start: no init_u as well
+    assert mlbm.load().mlbm_init_geometry(C.byref(d), None, C.byref(h)) == mlbm.E_ARG
+
+
 def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(mlbm, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(mlbm, "_lib", None)

@@ -353,6 +353,44 @@ def test_ellipsoid_96x192_16bit_step_kernel_at_full_size(prec, tol):
     g.close()
 
 
+@pytest.fixture(scope="module")
+def ellipsoid_96x192_small_radius_oracle():
+    """Oracle runs of the double-curved channel at the cross-sectional radii
+    R2/d = 5 and 10 (96 x 192 cross-section, one streamwise slab, tau raised
+    to the measured stability floor: 0.6669 and 0.5834), De 60, 1e-3
+    perturbation, 2000 steps."""
+    out = {}
+    for case in K.ellipsoid_96x192_cases(precision="f64", n2=1)[:2]:
+        init = K.perturbed_start(case, seed=21, amp=1e-3)
+        o = O.Sim(case, init_u=init)
+        o.step(2000)
+        out[case.r_inner] = (case, init, o.moments()[1], o.observables())
+    return out
+
+
+@pytest.mark.parametrize("R2", [5.0, 10.0])
+@pytest.mark.parametrize("prec", ["f32", "f16", pytest.param("bf16", marks=pytest.mark.xfail(
+    strict=True, reason="BF16 offset storage misses the 1e-3 velocity target at R2/d = 5 and 10 "
+                        "(measured 2.0e-3 and 2.3e-3 after 2000 steps; De within 4e-5)"))])
+def test_ellipsoid_96x192_small_radius_precision(ellipsoid_96x192_small_radius_oracle, R2, prec):
+    """Reduced-precision storage on the strongly curved cross sections of the
+    96 x 192 double-curved channel against the FP64 oracle after 2000 steps:
+    velocity relative L2 within the targets (FP32 1e-5, 16-bit offsets 1e-3)
+    and the Dean-number error printed beside it."""
+    case, init, u_o, obs_o = ellipsoid_96x192_small_radius_oracle[R2]
+    g = mlbm.Sim(case.replace(precision=prec), init_u=init)
+    g.step(2000)
+    _, u = g.moments()
+    err = _rel_l2(u, u_o)
+    de = g.vortex_intensity()[2]
+    de_err = abs(de / obs_o[2] - 1)
+    print(f"ellipsoid 96x1x192 R2/d={R2:g} tau {case.tau} {prec}: velocity rel L2 {err:.3e}; "
+          f"De {de:.4f} vs {obs_o[2]:.4f} ({de_err:.2e})")
+    bound = 1e-5 if prec == "f32" else 1e-3
+    assert err < bound and de_err < bound
+    g.close()
+
+
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 1e-5), ("f16", 2.0 ** -8), ("bf16", 2.0 ** -5)])
 def test_beyond_cache_step_kernel_at_full_size(prec, tol):
     """The instance bench.py's beyond-cache leg times (ellipsoid 96 x 192
@@ -500,3 +538,85 @@ def test_checkpoint_resume_is_bitwise(tmp_path):
     b.step(250)
     assert np.array_equal(a.get_f(), b.get_f())
     assert a.residual() == b.residual()
+
+
+# --------------------------------------------------------------------------
+# start recipes and buffers handled by the library (C ABI)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", [
+    K.cylinder_case(0.975, 16, 4, 32, 0.6, De=45.0, walls3=True),
+    K.ellipsoid_case(20.0, 10.0, 12, 4, 22, 0.6, De=60.0, precision="f64"),
+    K.cylinder_case(0.9, 17, 2, 8, 0.9, De=20.0, eq_walls=True),
+], ids=["cylinder", "ellipsoid", "cylinder-eq"])
+def test_library_built_start_equals_the_input_generator(case):
+    """target_De / perturb_amp / seed in the description: the library derives
+    the force from the Dean number and builds the closed-form start with the
+    seeded SplitMix64 perturbation itself; the state equals the one made from
+    the Python input generator's force and field to rounding. The two
+    evaluate the closed form A r ln r + B r + C / r with different libm and
+    2 x 2 solves, and its terms exceed the result by up to 1e5 (C / r against
+    v at R = 20), so they agree to 1e-12 to 2e-11 (measured), not to the last
+    bit."""
+    case = case.replace(precision="f64")
+    init = K.perturbed_start(case, seed=1411, amp=1e-3)
+    ref = mlbm.Sim(case, init_u=init)
+    got = mlbm.Sim(case.replace(force=0.0), start=dict(target_De=case.target_De, perturb_amp=1e-3, seed=1411))
+    fr, fg = ref.get_f(), got.get_f()
+    assert _rel_max(fg, fr) < 1e-10
+    ref.step(50)
+    got.step(50)
+    assert _rel_max(got.get_f(), ref.get_f()) < 1e-10
+    ref.close()
+    got.close()
+
+
+def test_cross_section_initial_field_layout():
+    """init_u given as one cross section [3][n1][n3] equals the same field
+    repeated over the theta slabs [3][N]."""
+    case = K.ellipsoid_case(20.0, 40.0, 12, 3, 16, 0.7, De=20.0, precision="f32")
+    full = K.perturbed_start(case, seed=4, amp=1e-2)
+    xsec = np.ascontiguousarray(full[:, :, 0, :])
+    a = mlbm.Sim(case, init_u=full)
+    b = mlbm.Sim(case, init_u=xsec)
+    assert np.array_equal(a.get_f(), b.get_f())
+    a.close()
+    b.close()
+
+
+def test_populations_on_a_device_buffer():
+    """mlbm_populations_device decodes into and encodes from a torch tensor."""
+    import torch
+    case = K.cylinder_case(0.9, 8, 4, 8, 0.8, De=10.0, walls3=True).replace(precision="f64")
+    g = mlbm.Sim(case, init_u=K.perturbed_start(case, seed=3, amp=0.05, U_nom=0.05))
+    g.step(7)
+    host = g.get_f()
+    dev = torch.zeros(41 * case.N, dtype=torch.float64, device="cuda")
+    g.populations_device(dev.data_ptr(), get=True)
+    assert np.array_equal(dev.cpu().numpy().reshape(host.shape), host)
+    dev.mul_(1.0 + 1e-3)
+    torch.cuda.synchronize()          # the library works on the handle's own stream
+    g.populations_device(dev.data_ptr(), get=False)
+    via_device = g.get_f()
+    g.set_f(dev.cpu().numpy())        # the host path encodes the same values
+    assert np.array_equal(via_device, g.get_f())
+    assert np.allclose(via_device, host * (1.0 + 1e-3), rtol=1e-14, atol=0.0)
+    g.close()
+
+
+def test_warm_start_network_file_roundtrip(tmp_path):
+    """A network saved with mlbm_warmstart_save and created again with
+    mlbm_warmstart_load predicts the same start field."""
+    net = mlbm.Net(32, 2, K.net_init_params(32, 2, seed=5))
+    path = str(tmp_path / "net.bin")
+    net.save(path)
+    other = mlbm.Net.load_file(path)
+    assert (other.hidden, other.depth) == (32, 2)
+    assert np.array_equal(other.params, net.params)
+    case = K.ellipsoid_case(20.0, 40.0, 12, 2, 16, 0.7, De=30.0)
+    a = net.predict(case, 30.0, 20.0, 40.0, 0.05)
+    b = other.predict(case, 30.0, 20.0, 40.0, 0.05)
+    assert np.array_equal(a, b)
+    with pytest.raises(mlbm.MlbmError):
+        (tmp_path / "bad.bin").write_bytes(b"MLBMNET1" + b"\x00" * 8)
+        mlbm.Net.load_file(str(tmp_path / "bad.bin"))
