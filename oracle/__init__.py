@@ -20,7 +20,7 @@ from . import build as _build
 Q = 41
 _lib = None
 
-KIND = {"flat": 0, "cylinder": 1, "ellipsoid": 2}
+KIND = {"flat": 0, "cylinder": 1, "ellipsoid": 2, "ellipsoid_full": 3}
 
 
 class OrcCase(C.Structure):
@@ -28,7 +28,7 @@ class OrcCase(C.Structure):
         ("kind", C.c_int), ("n1", C.c_int), ("n2", C.c_int), ("n3", C.c_int),
         ("walls", C.c_int), ("forcing_mode", C.c_int),
         ("r_inner", C.c_double), ("width", C.c_double), ("b", C.c_double),
-        ("tau", C.c_double), ("force", C.c_double),
+        ("tau", C.c_double), ("force", C.c_double), ("dtheta", C.c_double),
     ]
 
 
@@ -136,11 +136,12 @@ class Sim:
         oc = OrcCase(kind=KIND[case.kind], n1=case.n1, n2=case.n2, n3=case.n3,
                      walls=case.walls, forcing_mode=case.forcing_mode,
                      r_inner=case.r_inner, width=case.width, b=case.b,
-                     tau=case.tau, force=case.force)
+                     tau=case.tau, force=case.force, dtheta=getattr(case, "dtheta", 0.0))
         self.case = case
         self.shape = (case.n1, case.n2, case.n3)
         self.N = case.n1 * case.n2 * case.n3
-        self.NX = case.n1 * case.n3
+        self.n2g = case.n2 if case.kind == "ellipsoid_full" else 1
+        self.NX = case.n1 * self.n2g * case.n3
         self._iu = None
         if init_u is not None:
             self._iu = np.ascontiguousarray(init_u, np.float64).reshape(3 * self.N)
@@ -185,10 +186,11 @@ class Sim:
         dts = np.zeros(4)
         lib().orc_geometry(self._h, _ptr(g["ginv"]), _ptr(g["gcov"]), _ptr(g["sqrtg"]),
                            _ptr(g["gam"]), _ptr(g["fext"]), _ptr(g["coord"]), _ptr(dts))
-        n1, n3 = self.case.n1, self.case.n3
-        out = {"ginv": g["ginv"].reshape(n1, n3, 3, 3), "gcov": g["gcov"].reshape(n1, n3, 3, 3),
-               "sqrtg": g["sqrtg"].reshape(n1, n3), "gam": g["gam"].reshape(n1, n3, 3, 3, 3),
-               "fext": g["fext"].reshape(n1, n3, 3), "coord": g["coord"].reshape(n1, n3, 3),
+        # [n1][n3] per cross section, or [n1][n2][n3] when the metric depends on theta
+        xs = (self.case.n1, self.case.n3) if self.n2g == 1 else (self.case.n1, self.n2g, self.case.n3)
+        out = {"ginv": g["ginv"].reshape(xs + (3, 3)), "gcov": g["gcov"].reshape(xs + (3, 3)),
+               "sqrtg": g["sqrtg"].reshape(xs), "gam": g["gam"].reshape(xs + (3, 3, 3)),
+               "fext": g["fext"].reshape(xs + (3,)), "coord": g["coord"].reshape(xs + (3,)),
                "dt": dts[0], "s": dts[1:4].copy()}
         return out
 

@@ -41,6 +41,10 @@
  *     contravariant form is g^{i theta} K.
  *   - the ellipsoidal slab is streamwise periodic with the metric frozen at
  *     theta = 0 and the printed (theta independent) Christoffel symbols.
+ *   - the full ellipsoid (ORC_ELLIPSOID_FULL) evaluates the metric of Sec. IV
+ *     at every node's (r, theta, phi), non-diagonal off theta = 0, on a
+ *     theta sector centred on 0 that is periodic in theta; the theta spacing
+ *     is that of Sec. IV B unless the case gives one.
  *
  * Pins (tests that hold this code to facts fixed outside it):
  *   - lattice: the printed Table I (tests/golden/table1_weights.txt), the
@@ -293,7 +297,7 @@ void orc_collide(const double *f, const double *ginv, const double *gam, const d
 /* Geometry (Sec. III cylinder, Sec. IV ellipsoid with a = c = 1)            */
 /* ------------------------------------------------------------------------ */
 
-enum { ORC_FLAT = 0, ORC_CYLINDER = 1, ORC_ELLIPSOID = 2 };
+enum { ORC_FLAT = 0, ORC_CYLINDER = 1, ORC_ELLIPSOID = 2, ORC_ELLIPSOID_FULL = 3 };
 
 static void inverse3(const double g[9], double gi[9], double *det)
 {
@@ -367,11 +371,14 @@ typedef struct {
     double b;           /* ellipsoid semi-axis b                                 */
     double tau;         /* relaxation parameter                                  */
     double force;       /* covariant streamwise (axis 2) body force K            */
+    double dtheta;      /* full ellipsoid: theta spacing (0: Dr / (b r_i))       */
 } orc_case;
 
 typedef struct {
     orc_case cs;
-    long N, NX;         /* nodes, cross-section nodes (n1*n3)                    */
+    long N, NX;         /* nodes, geometry nodes (n1*n3, or n1*n2*n3 when the
+                           metric depends on theta)                             */
+    int n2g;            /* 1, or n2 for the full ellipsoid                       */
     double dt, s[3];    /* time step and scale factors s_i = Dx^i / Dt          */
     double *ginv;       /* [NX][9]  lattice inverse metric                       */
     double *gcov;       /* [NX][9]  lattice metric                               */
@@ -450,7 +457,7 @@ static void pull_source(const orc_case *cs, const int x[3], int q, int src[3], i
     *qsrc = (nref & 1) ? LOPP[q] : q;
 }
 
-static void geometry_point(const orc_sim *S, int x1, int x3, double out_coord[3])
+static void geometry_point(const orc_sim *S, int x1, int x2, int x3, double out_coord[3])
 {
     const orc_case *c = &S->cs;
     const double dr = S->dt * S->s[0];
@@ -468,19 +475,29 @@ static void geometry_point(const orc_sim *S, int x1, int x3, double out_coord[3]
         a1 = c->r_inner + (x1 + o1) * dr;                   /* r                    */
         a3 = (x3 + 0.5 - 0.5 * c->n3) * S->dt * S->s[2];    /* phi, symmetric about 0 */
     }
-    out_coord[0] = a1; out_coord[1] = 0.0; out_coord[2] = a3;
+    /* theta: 0 for the slab, a sector centred on 0 for the full ellipsoid */
+    const double a2 = c->kind == ORC_ELLIPSOID_FULL ? (x2 + 0.5 - 0.5 * c->n2) * S->dt * S->s[1] : 0.0;
+    out_coord[0] = a1; out_coord[1] = a2; out_coord[2] = a3;
+}
+
+/* Geometry index of node (x1, x2, x3). */
+static long geo_index(const orc_sim *S, int x1, int x2, int x3)
+{
+    return ((long)x1 * S->n2g + (S->n2g > 1 ? x2 : 0)) * S->cs.n3 + x3;
 }
 
 static void build_geometry(orc_sim *S)
 {
     const orc_case *c = &S->cs;
     for (int x1 = 0; x1 < c->n1; ++x1)
+        for (int x2 = 0; x2 < S->n2g; ++x2)
         for (int x3 = 0; x3 < c->n3; ++x3) {
-            long p = (long)x1 * c->n3 + x3;
+            long p = geo_index(S, x1, x2, x3);
             double *co = S->coord + 3 * p;
-            geometry_point(S, x1, x3, co);
+            geometry_point(S, x1, x2, x3, co);
             double g[9], gi[9], sg, gm[27];
-            orc_metric(c->kind, c->b, co[0], co[1], co[2], g, gi, &sg, gm);
+            orc_metric(c->kind == ORC_ELLIPSOID_FULL ? ORC_ELLIPSOID : c->kind, c->b, co[0], co[1], co[2],
+                       g, gi, &sg, gm);
             const double *s = S->s;
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j) {
@@ -501,14 +518,16 @@ orc_sim *orc_create(const orc_case *cs, const double *init_u)
     orc_sim *S = (orc_sim *)calloc(1, sizeof(orc_sim));
     S->cs = *cs;
     S->N = (long)cs->n1 * cs->n2 * cs->n3;
-    S->NX = (long)cs->n1 * cs->n3;
+    S->n2g = cs->kind == ORC_ELLIPSOID_FULL ? cs->n2 : 1;
+    S->NX = (long)cs->n1 * S->n2g * cs->n3;
     /* Dt = Dr = d / N_r: N_r fluid nodes between halfway walls, or n1 - 1
      * spacings between the wall nodes of equilibrium walls */
     S->dt = cs->width / ((cs->walls & ORC_WALL_EQ) ? cs->n1 - 1 : cs->n1);
     S->s[0] = 1.0; S->s[1] = 1.0; S->s[2] = 1.0;
-    if (cs->kind == ORC_ELLIPSOID) {                 /* rescaled spacings of Sec. IV B */
+    if (cs->kind == ORC_ELLIPSOID || cs->kind == ORC_ELLIPSOID_FULL) {   /* rescaled spacings of Sec. IV B */
         S->s[1] = 1.0 / (cs->b * cs->r_inner);
         S->s[2] = 1.0 / cs->r_inner;
+        if (cs->kind == ORC_ELLIPSOID_FULL && cs->dtheta > 0.0) S->s[1] = cs->dtheta / S->dt;
     }
     S->ginv = (double *)malloc(sizeof(double) * 9 * S->NX);
     S->gcov = (double *)malloc(sizeof(double) * 9 * S->NX);
@@ -536,7 +555,7 @@ orc_sim *orc_create(const orc_case *cs, const double *init_u)
     for (int x1 = 0; x1 < cs->n1; ++x1)
         for (int x2 = 0; x2 < cs->n2; ++x2)
             for (int x3 = 0; x3 < cs->n3; ++x3) {
-                long n = node_index(cs, x1, x2, x3), p = (long)x1 * cs->n3 + x3;
+                long n = node_index(cs, x1, x2, x3), p = geo_index(S, x1, x2, x3);
                 double U[3] = {0, 0, 0};
                 if (init_u && !is_wall_row(cs, x1))
                     for (int i = 0; i < 3; ++i) U[i] = init_u[i * S->N + n] / S->s[i];
@@ -561,8 +580,8 @@ static void gather(const orc_sim *S, const double *state, long n, double fin[Q])
 static long xsec_of(const orc_sim *S, long n)
 {
     const long n23 = (long)S->cs.n2 * S->cs.n3;
-    long x1 = n / n23, x3 = n % S->cs.n3;
-    return x1 * S->cs.n3 + x3;
+    long x1 = n / n23, x2 = (n / S->cs.n3) % S->cs.n2, x3 = n % S->cs.n3;
+    return geo_index(S, (int)x1, (int)x2, (int)x3);
 }
 
 static int row_of(const orc_sim *S, long n) { return (int)(n / ((long)S->cs.n2 * S->cs.n3)); }
@@ -728,7 +747,7 @@ void orc_observables_u(const orc_sim *S, const double *u, double *omega_mean, do
             }
         for (int x1 = 0; x1 < n1; ++x1)
             for (int x3 = 0; x3 < n3; ++x3) {
-                long p = (long)x1 * n3 + x3, n = node_index(c, x1, x2, x3);
+                long p = geo_index(S, x1, x2, x3), n = node_index(c, x1, x2, x3);
                 const double r = S->coord[3 * p], ph = S->coord[3 * p + 2];
                 const int eq = (c->walls & ORC_WALL_EQ) != 0;
                 double d3ur = ddx(ur, n1, n3, 2, (c->walls >> 2) & 1, x1, x3, h3);
@@ -737,7 +756,7 @@ void orc_observables_u(const orc_sim *S, const double *u, double *omega_mean, do
                 double vort = fabs(d3ur - d1uz), uth = u[1 * N + n];
                 double wv, wo, ws;
                 if (c->kind == ORC_CYLINDER) { wv = r; wo = r; ws = 1.0; }
-                else if (c->kind == ORC_ELLIPSOID) { wv = r * r * c->b * cos(ph); wo = r * c->b * cos(ph); ws = r; }
+                else if (c->kind >= ORC_ELLIPSOID) { wv = r * r * c->b * cos(ph); wo = r * c->b * cos(ph); ws = r; }
                 else { wv = 1.0; wo = 1.0; ws = 1.0; }
                 v_num += tw * uth * wv * h1 * h3;
                 om_num += tw * vort * wo * h1 * h3;

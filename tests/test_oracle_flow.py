@@ -312,18 +312,23 @@ def test_laminar_cylinder_profile_and_dean_number():
 @pytest.mark.parametrize("case", [
     K.cylinder_case(0.9, 8, 2, 8, 0.8, De=10.0, walls3=True),
     K.ellipsoid_case(20.0, 5.0, 12, 2, 16, 0.6, De=5.0),
-], ids=["cylinder-walls13", "ellipsoid"])
+    K.Case(kind="ellipsoid_full", n1=6, n2=8, n3=6, walls=1, r_inner=10.0, width=1.0, b=1.5,
+           tau=0.7, force=1e-4, dtheta=0.15),
+], ids=["cylinder-walls13", "ellipsoid", "ellipsoid-full"])
 def test_mass_budget_is_exact_each_step(case):
     """sum f(t+1) - sum f(t) = sum_x sum_lambda F_lambda = sum_x -2 rho' U^i Gamma^j_ij
     (streaming with bounce-back is a permutation, BGK keeps sum f)."""
     init = K.perturbed_start(case, seed=5, amp=0.05)
     S = O.Sim(case, init_u=init)
     geo = S.geometry()
-    trace = np.einsum("xzjji->xzi", geo["gam"])          # Gamma^j_ij per cross-section node
+    gam, sqrtg = geo["gam"], geo["sqrtg"]
+    if gam.ndim == 5:                                      # per cross section: the same for every slab
+        gam, sqrtg = gam[:, None], sqrtg[:, None]
+    trace = np.einsum("xyzjji->xyzi", gam)                # Gamma^j_ij per node
     for _ in range(5):
         rho, u, U = S.moments()
-        rp = rho / geo["sqrtg"][:, None, :]
-        src = -2.0 * np.einsum("xyz,ixyz,xzi->", rp, U, trace)
+        rp = rho / sqrtg
+        src = -2.0 * np.einsum("xyz,ixyz,xyzi->", rp, U, np.broadcast_to(trace, rp.shape + (3,)))
         m0 = S.get_f().sum()
         S.step(1)
         m1 = S.get_f().sum()

@@ -2,6 +2,8 @@
 its streaming with walls, against the Levi-Civita connection computed by
 finite differences of the printed metric, the Cartesian embedding of the
 coordinates, and the permutation property of streaming with bounce-back."""
+import math
+
 import numpy as np
 import pytest
 
@@ -178,3 +180,53 @@ def test_bounce_back_worked_examples():
     assert pm[node(4, 0, 1), q] == node(3, 1, 0) * 41 + q
     q = q_of((-3, -3, 3))
     assert pm[node(4, 0, 1), q] == node(7, 3, (1 - 3) % 10) * 41 + q
+
+
+FULL = K.Case(kind="ellipsoid_full", n1=6, n2=8, n3=6, walls=1, r_inner=10.0, width=1.0, b=math.sqrt(2.0),
+              tau=0.7, force=1e-4, dtheta=0.15)
+
+
+def test_full_ellipsoid_lattice_geometry_at_any_theta():
+    """The full double-curved geometry (Sec. IV metric at every node's
+    theta, non-diagonal off theta = 0): in lattice coordinates the metric is
+    g_ij s_i s_j and the per-step Christoffels are its Levi-Civita
+    connection, on a sector of theta in [-0.6, 0.6]."""
+    S = O.Sim(FULL)
+    geo = S.geometry()
+    dt, s = geo["dt"], geo["s"]
+    dx = dt * s
+    thetas = []
+    for x1 in (0, FULL.n1 - 1):
+        for x2 in (0, 3, FULL.n2 - 1):
+            for x3 in (0, FULL.n3 - 1):
+                co = geo["coord"][x1, x2, x3]
+                thetas.append(co[1])
+
+                def ghat(X):
+                    return O.metric("ellipsoid", FULL.b, *(X * dx))[0] * np.outer(s, s)
+
+                X0 = co / dx
+                gl = ghat(X0)
+                assert abs(gl[0, 1]) > 1e-3                    # non-diagonal off theta = 0
+                assert np.abs(geo["gcov"][x1, x2, x3] - gl).max() < 1e-12
+                assert np.abs(geo["ginv"][x1, x2, x3] @ gl - np.eye(3)).max() < 1e-12
+                Gl = _lc_fd(ghat, X0, h=1e-3)
+                assert np.all(np.abs(geo["gam"][x1, x2, x3] - Gl) < 1e-8 * (1.0 + np.abs(Gl)))   # FD O(h^2)
+                # covariant theta force: F^i = Dt g^{i theta} K / s_i
+                gi = np.linalg.inv(O.metric("ellipsoid", FULL.b, *co)[0])
+                assert np.allclose(geo["fext"][x1, x2, x3], dt * gi[:, 1] * FULL.force / s, rtol=1e-12, atol=0)
+    assert min(thetas) < -0.5 and max(thetas) > 0.5
+
+
+def test_full_ellipsoid_at_b1_is_the_theta_independent_slab():
+    """With b = 1 the metric does not depend on theta, so the full geometry
+    steps exactly like the slab frozen at theta = 0 (to rounding)."""
+    full = FULL.replace(b=1.0, dtheta=0.0)
+    slab = full.replace(kind="ellipsoid")
+    init = K.perturbed_start(slab, seed=2, amp=0.05, U_nom=0.05)
+    a = O.Sim(full, init_u=init)
+    c = O.Sim(slab, init_u=init)
+    a.step(20)
+    c.step(20)
+    fa, fc = a.get_f(), c.get_f()
+    assert np.abs(fa - fc).max() < 1e-14 * np.abs(fc).max()

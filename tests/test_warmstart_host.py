@@ -36,9 +36,9 @@ def test_fallback_accounting(monkeypatch):
     cases = [K.ellipsoid_case(20.0, 30.0, 8, 2, 16, 0.6, De=De) for De in (30.0, 40.0, 50.0)]
     calls = []
 
-    def fake_run(cs, inits, tol, max_steps, chunk=20000, log=None, stream=None):
+    def fake_run(cs, inits, tol, max_steps, chunk=20000, log=None, stream=None, stall_chunks=None):
         calls.append((len(cs), max_steps, [float(u[0]) for u in inits]))
-        if len(calls) == 1:      # warm batch: instance 1 stalls
+        if len(calls) == 1:      # warm batch: instance 1 reaches the budget
             steps = np.array([1200, max_steps, 900])
             status = np.array([0, 1, 0], np.int32)
             return FakeBatch([10.0, 11.0, 12.0]), steps, status, 0.5
@@ -63,7 +63,7 @@ def test_no_fallback_without_budget(monkeypatch):
     cases = [K.ellipsoid_case(20.0, 30.0, 8, 2, 16, 0.6, De=30.0)]
     calls = []
 
-    def fake_run(cs, inits, tol, max_steps, chunk=20000, log=None, stream=None):
+    def fake_run(cs, inits, tol, max_steps, chunk=20000, log=None, stream=None, stall_chunks=None):
         calls.append(max_steps)
         return FakeBatch([1.0]), np.array([max_steps]), np.array([1], np.int32), 0.1
 
@@ -71,3 +71,27 @@ def test_no_fallback_without_budget(monkeypatch):
     monkeypatch.setattr(W, "predict_inits", lambda net, cs: [np.zeros(1)])
     _, steps, status, _, _, redo, _, _ = W.warm_start_run(None, cases, [np.zeros(1)], 1e-6, 5000)
     assert calls == [5000] and redo == [] and status.tolist() == [1] and steps.tolist() == [5000]
+
+
+def test_stalled_instances_fall_back_early(monkeypatch):
+    """An instance the warm batch retires as stalled (status 3) before the
+    budget is rerun from its plain start; its steps count the warm steps it
+    took before stalling."""
+    cases = [K.ellipsoid_case(20.0, 30.0, 8, 2, 16, 0.6, De=De) for De in (30.0, 40.0)]
+    calls = []
+
+    def fake_run(cs, inits, tol, max_steps, chunk=20000, log=None, stream=None, stall_chunks=None):
+        calls.append((len(cs), max_steps, stall_chunks))
+        if len(calls) == 1:
+            return FakeBatch([10.0, 11.0]), np.array([15000, 800]), np.array([3, 0], np.int32), 0.5
+        return FakeBatch([30.0]), np.array([4000]), np.zeros(1, np.int32), 0.3
+
+    monkeypatch.setattr(W, "run_to_steady", fake_run)
+    monkeypatch.setattr(W, "predict_inits", lambda net, cs: [np.zeros(1) for _ in cs])
+    fields, steps, status, _, _, redo, _, _ = W.warm_start_run(None, cases, [np.zeros(1)] * 2, 1e-6, 150000,
+                                                               fallback_after=60000, stall_chunks=3)
+    assert calls[0] == (2, 60000, 3) and calls[1] == (1, 150000, None)
+    assert redo == [0]
+    assert steps.tolist() == [15000 + 4000, 800]
+    assert status.tolist() == [0, 0]
+    assert float(fields[0][1][0]) == 30.0
