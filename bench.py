@@ -266,12 +266,17 @@ def beyond_cache_leg(precision, steps=500, warmup=100, block=0, grid=0):
             "health": health}
 
 
-def critical_dean_leg(tol=1e-7):
-    """Critical Dean numbers (onset of 2, 4 and 6 cells) of the stable
-    curvature pairs of the batched sweep, at N_r = 32, by batched bisection to
-    1 % brackets: once from plain starts, once warm-started by a network
-    trained on the sweep's own first-round fields. Reports both and their
-    largest relative difference (measured De, bracket midpoints)."""
+def critical_dean_leg(tol=1e-7, grid_points=9):
+    """Critical Dean numbers (onset of 2, 4 and 6 cells) of the 8 curvature
+    pairs of the batched sweep at N_r = 32, by batched bisection to 1 %
+    brackets. Each pair runs at the larger of the Mach-rule tau and its
+    measured stability floor, over De from 20 to 200 or to the De where its
+    mean lattice speed reaches Mach 0.3 at that tau. Once from plain starts;
+    once with every run (first round included) started from a network
+    trained on the plain sweep's converged first-round fields, falling back
+    to the plain start where a warm run stalls. Reports both, their largest
+    relative difference (measured De, bracket midpoints), the fallbacks per
+    round and how many bracket ends finished from the warm start."""
     from paper_1411_3133_amd import cases as K
     from paper_1411_3133_amd import sweep
 
@@ -279,38 +284,48 @@ def critical_dean_leg(tol=1e-7):
         print(msg, file=sys.stderr, flush=True)
 
     pairs = K.critical_pairs()
-    grid = [20.0 + 5.0 * i for i in range(13)]
-    res = {}
-    for warm in (False, True):
-        log(f"critical De: {'warm' if warm else 'plain'} starts")
-        res[warm] = sweep.critical_dean(pairs, grid, tol=tol, max_steps=400000, warm=warm, log=log)
+
+    def grid(top):
+        return sweep.even_grid(20.0, top, grid_points)
+
+    log("critical De: plain starts")
+    plain = sweep.critical_dean(pairs, grid, tol=tol, max_steps=400000, log=log)
+    t0 = time.perf_counter()
+    net = sweep.train_on(plain["dataset"])
+    t_train = time.perf_counter() - t0
+    log("critical De: warm starts")
+    warm = sweep.critical_dean(pairs, grid, tol=tol, max_steps=400000, net=net, log=log)
 
     def mid(x):
         return None if None in x else 0.5 * (x[0] + x[1])
 
-    onsets, diffs = {}, []
-    for key, a in res[False]["onsets"].items():
-        b = res[True]["onsets"][key]
+    onsets, diffs, warm_ends = {}, [], 0
+    for key, a in plain["onsets"].items():
+        b = warm["onsets"][key]
         ma, mb = mid(a["De_measured"]), mid(b["De_measured"])
         if ma is None and mb is None:
             continue
         onsets[key] = [None if ma is None else round(ma, 3), None if mb is None else round(mb, 3)]
+        warm_ends += sum(1 for w in b["warm_at_ends"] if w)
         if ma is not None and mb is not None:
             diffs.append(abs(ma - mb) / ma)
     return {
-        "workload": f"{len(pairs)} curvature pairs of the batched sweep (R2/d >= 18), ellipsoid slabs 32x4xn3, "
-                    f"De grid 20..80 then bisection to 1 % brackets, FP64, residual {tol:g}",
+        "workload": f"{len(pairs)} curvature pairs of the batched sweep, ellipsoid slabs 32x4xn3, tau per pair "
+                    f"(Mach rule, raised to the stability floor), De grid of {grid_points} from 20 to the pair's "
+                    f"top (200 or Mach 0.3), then bisection to 1 % brackets, FP64, residual {tol:g}",
+        "pairs": {name: {"tau": make(30.0).tau, "R2_d": round(make(30.0).r_inner, 3), "De_top": round(top, 1)}
+                  for name, make, top in pairs},
         "onsets_plain_warm": onsets,
-        # onset read off the <omega>(measured De) curve of converged runs,
-        # the paper's way of reading it, beside the 2-cell onsets above
-        "omega_knees_plain_warm": {name: [None if res[w]["knees"][name] is None else round(res[w]["knees"][name], 3)
-                                          for w in (False, True)] for name in res[False]["knees"]},
+        "omega_knees_plain_warm": {name: [None if r["knees"][name] is None else round(r["knees"][name], 3)
+                                          for r in (plain, warm)] for name in plain["knees"]},
         "max_rel_diff": round(max(diffs), 5) if diffs else None,
         "within_1pct": f"{sum(d <= 0.01 for d in diffs)}/{len(diffs)}",
-        "seconds_plain": res[False]["seconds"], "seconds_warm": res[True]["seconds"],
-        "train_seconds": res[True]["train_seconds"],
-        "instance_steps_plain": sum(r["instance_steps"] for r in res[False]["rounds"]),
-        "instance_steps_warm": sum(r["instance_steps"] for r in res[True]["rounds"]),
+        "bracket_ends_finished_warm": warm_ends,
+        "warm_fallbacks_per_round": [r["fallbacks"] for r in warm["rounds"]],
+        "warm_instances_per_round": [r["instances"] for r in warm["rounds"]],
+        "seconds_plain": plain["seconds"], "seconds_warm": warm["seconds"], "train_seconds": round(t_train, 2),
+        "instance_steps_plain": sum(r["instance_steps"] for r in plain["rounds"]),
+        "instance_steps_warm": sum(r["instance_steps"] for r in warm["rounds"]),
     }
 
 

@@ -48,7 +48,10 @@ typedef enum {
 typedef enum {
     MLBM_FLAT = 0,        /* Cartesian, g = delta, Gamma = 0                       */
     MLBM_CYLINDER = 1,    /* (r, theta, z), Sec. III                               */
-    MLBM_ELLIPSOID = 2    /* (r, theta, phi) with a = c = 1, Sec. IV, at theta = 0  */
+    MLBM_ELLIPSOID = 2,   /* (r, theta, phi) with a = c = 1, Sec. IV, at theta = 0  */
+    MLBM_ELLIPSOID_FULL = 3 /* the same coordinates with the metric of Sec. IV at
+                           every node's theta (non-diagonal off theta = 0), on a
+                           theta sector centred on 0, periodic in theta      */
 } mlbm_kind;
 
 typedef enum {
@@ -118,7 +121,10 @@ enum { MLBM_FORCING_IMPROVED = 0, MLBM_FORCING_OLD = 1 };
  *                2^-52 - 1, z_i = splitmix64(i ^ (seed * 0x100000001B3)),
  *                i = (component n1 + x1) n3 + x3); init_u must be NULL.
  *  seed          key of the start perturbation.
- *  init_u_xsec   layout of init_u, see above. */
+ *  init_u_xsec   layout of init_u, see above.
+ *  dtheta        MLBM_ELLIPSOID_FULL: theta spacing of the sector, nodes at
+ *                theta = (x2 + 1/2 - n2/2) dtheta; 0 means the spacing of
+ *                Sec. IV B, Dr / (b r_i).  Ignored by the other kinds. */
 typedef struct {
     int32_t kind;
     int32_t n1, n2, n3;
@@ -137,6 +143,7 @@ typedef struct {
     uint64_t seed;
     int32_t init_u_xsec;
     int32_t reserved;        /* 0 */
+    double dtheta;
 } mlbm_desc;
 
 typedef struct mlbm_sim_s *mlbm_handle;
@@ -249,9 +256,21 @@ mlbm_status mlbm_batch_step(mlbm_batch b, int64_t n);
 /* Advance whole windows; an instance retires when its residual is <= tol,
  * when it becomes unstable or after max_steps.  steps[i] receives the steps
  * instance i took, residual[i] its last residual, status[i] 0 converged,
- * 1 hit max_steps, 2 unstable (each array may be NULL). */
+ * 1 hit max_steps, 2 unstable, 3 retired by the caller (each array may be
+ * NULL). */
 mlbm_status mlbm_batch_run_until(mlbm_batch b, double tol, int64_t max_steps, int64_t *steps,
                                  double *residual, int32_t *status);
+
+/* Retirement across calls.  By default mlbm_batch_run_until brings every
+ * instance back when it returns.  With mlbm_batch_keep_retired(b, 1) the
+ * instances it retired (converged, unstable, at their step cap) stay out of
+ * later mlbm_batch_step / mlbm_batch_run_until calls, keeping their state
+ * and step count, and mlbm_batch_retire(b, i) retires instance i at once
+ * (its status then reads 3); mlbm_batch_keep_retired(b, 0) brings every
+ * instance back.  Retiring needs the batch on a window boundary (a step
+ * count that is a multiple of check_every; E_STATE otherwise). */
+mlbm_status mlbm_batch_keep_retired(mlbm_batch b, int on);
+mlbm_status mlbm_batch_retire(mlbm_batch b, int i);
 
 /* Non-owning view of instance i, usable until the batch is destroyed; every
  * single-instance query above (moments, vortex_intensity, residual,

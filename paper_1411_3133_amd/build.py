@@ -22,13 +22,26 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def _up_to_date(obj: str, src: str) -> bool:
+    """The object is newer than its source, every header and the flags."""
+    if not os.path.exists(obj):
+        return False
+    deps = [src, __file__] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    deps.append(os.path.join(HERE, "..", "include", "mlbm.h"))
+    return all(os.path.getmtime(obj) >= os.path.getmtime(d) for d in deps)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (or, with incremental, only those whose object is
+    out of date) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     procs = []
     objs = []
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         objs.append(obj)
+        if incremental and _up_to_date(obj, os.path.join(CSRC, src)):
+            continue
         cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -54,4 +67,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)

@@ -28,7 +28,7 @@ import numpy as np
 # number into a nominal force (Sec. II).
 CS2_NOMINAL = 1.0 - math.sqrt(0.4)
 
-KINDS = ("flat", "cylinder", "ellipsoid")
+KINDS = ("flat", "cylinder", "ellipsoid", "ellipsoid_full")
 PRECISIONS = ("f64", "f32", "f16", "bf16", "f32c64")
 WALL_AXIS1 = 1
 WALL_AXIS3 = 4
@@ -55,6 +55,7 @@ class Case:
     check_every: int = 100
     target_De: Optional[float] = None
     label: str = ""
+    dtheta: float = 0.0    # full ellipsoid: theta spacing of the sector (0: Sec. IV B, Dr / (b r_i))
 
     @property
     def N(self) -> int:
@@ -77,7 +78,7 @@ class Case:
         """Streamwise curvature radius of the inner wall (Sec. III, Sec. IV)."""
         if self.kind == "cylinder":
             return self.r_inner
-        if self.kind == "ellipsoid":
+        if self.kind in ("ellipsoid", "ellipsoid_full"):
             return self.r_inner * self.b * self.b
         return math.inf
 
@@ -189,7 +190,7 @@ def node_coords(case: Case):
     x1 = (np.arange(case.n1) + (0.0 if case.eq_walls else 0.5)) * dt
     if case.kind != "flat":
         x1 = case.r_inner + x1
-    if case.kind == "ellipsoid":
+    if case.kind in ("ellipsoid", "ellipsoid_full"):
         s3 = 1.0 / case.r_inner
         x3 = (np.arange(case.n3) + 0.5 - 0.5 * case.n3) * dt * s3
     else:
@@ -231,7 +232,7 @@ def perturbed_start(case: Case, seed: int, amp: float = 1e-4,
     scale = np.ones((3, case.n1, 1, case.n3))
     if case.kind == "cylinder":
         scale[1] = 1.0 / r[:, None, None]
-    elif case.kind == "ellipsoid":
+    elif case.kind in ("ellipsoid", "ellipsoid_full"):
         scale[1] = 1.0 / (r[:, None, None] * case.b * np.cos(x3)[None, None, :])
         scale[2] = 1.0 / r[:, None, None]
     return u + amp * U_nom * xi * scale
@@ -377,15 +378,25 @@ def warmstart_cases(n: int, seed: int, n1: int = 24, n3: int = 48, ratio_lo: flo
     return out
 
 
-def critical_pairs(seed: int = 3133, n1: int = 32, De_max: float = 80.0, min_R2: float = 18.0,
-                   precision: str = "f64", n_pairs: int = 8):
+def mach_limited_De(n1: int, tau: float, width: float, R: float, mach: float = 0.3) -> float:
+    """The Dean number at which the mean lattice speed reaches `mach` c_s
+    (the inverse of tau_for_mach)."""
+    Re = mach * n1 / ((tau - 0.5) * math.sqrt(CS2_NOMINAL))
+    return Re * math.sqrt(width / R)
+
+
+def critical_pairs(seed: int = 3133, n1: int = 32, De_max: float = 200.0, min_R2: float = 0.0,
+                   precision: str = "f64", n_pairs: int = 8, tau: Optional[float] = None):
     """Curvature pairs of the batched sweep (uneven_ellipsoid_batch with the same
-    seed) for the critical-De study: pairs with R2/d >= min_R2 (the scheme's
-    stable range at this tau), each at n1 x 4 x n3 with the pair's
-    cross-section aspect n3/n1 kept (n3 rounded to a multiple of 4, >= 8),
-    one tau from the Mach rule at De_max. Returns [(label, make(De) -> Case)]."""
+    seed) for the critical-De study, each at n1 x 4 x n3 with the pair's
+    cross-section aspect n3/n1 kept (n3 rounded to a multiple of 4, >= 8).
+    tau per pair: the given one, or the larger of the Mach rule at De_max and
+    the measured stability floor of the pair's r_i/d. A pair's De range ends
+    at De_max or where the mean lattice speed reaches Mach 0.3 at that tau,
+    whichever is lower (small cross-sectional radii need the larger tau,
+    which moves Mach 0.3 to a lower De). Pairs with R2/d < min_R2 are left
+    out. Returns [(label, make(De) -> Case, De_top)]."""
     u = uniform_pm1(seed, 4 * n_pairs + n_pairs * 8, stream=4) * 0.5 + 0.5
-    tau = round(tau_for_mach(n1, De_max, 1.0, 20.0), 4)
     out = []
     for p in range(n_pairs):
         ratio = math.exp(math.log(0.25) + u[4 * p] * (math.log(4.0) - math.log(0.25)))
@@ -393,13 +404,18 @@ def critical_pairs(seed: int = 3133, n1: int = 32, De_max: float = 80.0, min_R2:
         if R2 < min_R2:
             continue
         n1_c4 = 32 + int(u[4 * p + 1] * 65)
-        n3_c4 = max(16, ((64 + int(u[4 * p + 2] * 193)) // 16) * 16)
+        n3_c4 = 64 + int(u[4 * p + 2] * 193)
         n3 = max(8, int(round(n3_c4 * n1 / n1_c4 / 4.0)) * 4)
+        t = tau
+        if t is None:
+            t = max(round(tau_for_mach(n1, De_max, 1.0, 20.0), 4),
+                    math.ceil(stability_floor_tau(R2, n1) * 1e4) / 1e4)
+        top = min(De_max, mach_limited_De(n1, t, 1.0, 20.0))
 
-        def make(De, R2=R2, n3=n3, p=p):
-            return ellipsoid_case(20.0, R2, n1, 4, n3, tau, De=float(De), precision=precision,
+        def make(De, R2=R2, n3=n3, p=p, t=t):
+            return ellipsoid_case(20.0, R2, n1, 4, n3, t, De=float(De), precision=precision,
                                   label=f"pair{p}")
-        out.append((f"pair{p}", make))
+        out.append((f"pair{p}", make, top))
     return out
 
 

@@ -58,8 +58,8 @@ struct Instance {
 struct GeoEntry {
     double *ptr = nullptr;
     float *fptr = nullptr;     // the same values rounded to FP32
-    int kind, n1, n3, eq;
-    double r_inner, width, b;
+    int kind, n1, n2, n3, eq;
+    double r_inner, width, b, dtheta;
 };
 
 }  // namespace
@@ -127,6 +127,7 @@ struct Batch {
     hipGraphExec_t graph = nullptr;
     hipGraph_t graph_src = nullptr;
     bool graph_valid = false;
+    bool keep_retired = false; // retired instances stay out of later steps
 
     double *d_scratch = nullptr;
     size_t scratch_bytes = 0;
@@ -149,7 +150,12 @@ struct mlbm_batch_s {
 
 namespace {
 
-int pattern_for_kind(int kind) { return kind == MLBM_ELLIPSOID ? PAT_ELL : PAT_CYL; }
+int pattern_for_kind(int kind)
+{
+    return kind == MLBM_ELLIPSOID_FULL ? PAT_GEN : kind == MLBM_ELLIPSOID ? PAT_ELL : PAT_CYL;
+}
+
+bool ellipsoidal(int kind) { return kind == MLBM_ELLIPSOID || kind == MLBM_ELLIPSOID_FULL; }
 
 // Storage pitch of x3: n3 rounded up to 16 values, so that every x2 row of
 // every population plane starts on a 64-byte boundary (measured on the
@@ -161,7 +167,9 @@ size_t storage_values(const InstDesc &h) { return (size_t)Q * h.n1 * h.Pp; }
 
 mlbm_status validate(const mlbm_desc &d)
 {
-    if (d.kind < 0 || d.kind > 2) return fail(MLBM_E_ARG, "kind must be MLBM_FLAT, MLBM_CYLINDER or MLBM_ELLIPSOID");
+    if (d.kind < 0 || d.kind > 3)
+        return fail(MLBM_E_ARG, "kind must be MLBM_FLAT, MLBM_CYLINDER, MLBM_ELLIPSOID or MLBM_ELLIPSOID_FULL");
+    if (!(d.dtheta >= 0.0) || !std::isfinite(d.dtheta)) return fail(MLBM_E_ARG, "dtheta must be >= 0");
     if (d.n1 < 1 || d.n2 < 1 || d.n3 < 1) return fail(MLBM_E_ARG, "n1, n2, n3 must be >= 1");
     if ((d.walls & ~(MLBM_WALL_AXIS1 | MLBM_WALL_AXIS3 | MLBM_WALL_EQUILIBRIUM)) != 0)
         return fail(MLBM_E_ARG, "walls: unknown bits");
@@ -190,7 +198,7 @@ mlbm_status validate(const mlbm_desc &d)
     if (d.init_u_xsec != 0 && d.init_u_xsec != 1) return fail(MLBM_E_ARG, "init_u_xsec must be 0 or 1");
     if (d.reserved != 0) return fail(MLBM_E_ARG, "reserved must be 0");
     if (d.kind != MLBM_FLAT && !(d.r_inner > 0.0)) return fail(MLBM_E_ARG, "r_inner must be > 0");
-    if (d.kind == MLBM_ELLIPSOID) {
+    if (ellipsoidal(d.kind)) {
         if (!(d.b > 0.0)) return fail(MLBM_E_ARG, "b must be > 0");
         const double dphi = d.width / d.n1 / d.r_inner;
         if (!(0.5 * d.n3 * dphi < 1.5)) return fail(MLBM_E_ARG, "phi sector must stay inside |phi| < 1.5");
@@ -206,9 +214,10 @@ void scales(const mlbm_desc &d, double &dt, double s[3])
     // wall nodes of equilibrium walls
     dt = d.width / (eq_walls(d) ? d.n1 - 1 : d.n1);
     s[0] = s[1] = s[2] = 1.0;
-    if (d.kind == MLBM_ELLIPSOID) {   // rescaled spacings of Sec. IV B
+    if (ellipsoidal(d.kind)) {   // rescaled spacings of Sec. IV B
         s[1] = 1.0 / (d.b * d.r_inner);
         s[2] = 1.0 / d.r_inner;
+        if (d.kind == MLBM_ELLIPSOID_FULL && d.dtheta > 0.0) s[1] = d.dtheta / dt;
     }
 }
 
@@ -246,6 +255,7 @@ double curved_mean(double ri, double ro, double K, double nu)
 }
 
 double stream_radius(const mlbm_desc &d) { return d.kind == MLBM_CYLINDER ? d.r_inner : d.r_inner * d.b * d.b; }
+// (every ellipsoidal kind: the streamwise radius at theta = 0)
 
 // Mean streamwise speed implied by De (Eq. (8)): De nu / d (flat: the
 // Reynolds number), over sqrt(d / R) for curved channels.
@@ -356,6 +366,11 @@ uint32_t desc_salt(const mlbm_desc &d)
     for (double x : vals) {
         uint64_t u;
         memcpy(&u, &x, sizeof(u));
+        add(u);
+    }
+    if (d.dtheta != 0.0) {   // only the full ellipsoid sets it; other salts stay as they were
+        uint64_t u;
+        memcpy(&u, &d.dtheta, sizeof(u));
         add(u);
     }
     return h;
@@ -506,6 +521,22 @@ mlbm_status advance(Batch *B, int64_t n)
     return MLBM_OK;
 }
 
+// Every instance stops on a window boundary, so every step count is a
+// multiple of the even K and all instances share the buffer parity of the
+// batch clock: they can all be stepped again together.
+mlbm_status reactivate_all(Batch *B)
+{
+    bool changed = false;
+    int64_t tmax = 0;
+    for (auto &I : B->inst) {
+        changed |= !I.active;
+        I.active = true;
+        tmax = std::max(tmax, I.t);
+    }
+    B->t = tmax;
+    return changed ? build_tiles(B) : MLBM_OK;
+}
+
 mlbm_status read_ws(Batch *B, std::vector<WindowState> &ws)
 {
     ws.resize(B->inst.size());
@@ -519,28 +550,31 @@ GeoEntry *find_or_make_geo(Batch *B, const mlbm_desc &d, int &key, mlbm_status &
     for (size_t k = 0; k < B->geos.size(); ++k) {
         GeoEntry &g = B->geos[k];
         if (g.kind == d.kind && g.n1 == d.n1 && g.n3 == d.n3 && g.r_inner == d.r_inner && g.width == d.width &&
-            g.b == d.b && g.eq == (int)eq_walls(d)) {
+            g.b == d.b && g.eq == (int)eq_walls(d) &&
+            (d.kind != MLBM_ELLIPSOID_FULL || (g.n2 == d.n2 && g.dtheta == d.dtheta))) {
             key = (int)k;
             st = MLBM_OK;
             return &g;
         }
     }
     GeoEntry g{};
-    g.kind = d.kind; g.n1 = d.n1; g.n3 = d.n3; g.r_inner = d.r_inner; g.width = d.width; g.b = d.b;
+    g.kind = d.kind; g.n1 = d.n1; g.n2 = d.n2; g.n3 = d.n3; g.r_inner = d.r_inner; g.width = d.width; g.b = d.b;
     g.eq = (int)eq_walls(d);
-    const int n3g = d.kind == MLBM_ELLIPSOID ? d.n3 : 1;
-    hipError_t e = hipMalloc(&g.ptr, sizeof(double) * NGEO * d.n1 * n3g);
+    g.dtheta = d.dtheta;
+    const int n3g = ellipsoidal(d.kind) ? d.n3 : 1;
+    const int n2g = d.kind == MLBM_ELLIPSOID_FULL ? d.n2 : 1;
+    hipError_t e = hipMalloc(&g.ptr, sizeof(double) * NGEO * d.n1 * n2g * n3g);
     if (e != hipSuccess) {
         st = fail(MLBM_E_OOM, "geometry allocation failed");
         return nullptr;
     }
     GeoParams p{};
-    p.kind = d.kind; p.n1 = d.n1; p.n3 = d.n3; p.n3g = n3g;
+    p.kind = d.kind; p.n1 = d.n1; p.n2 = d.n2; p.n3 = d.n3; p.n2g = n2g; p.n3g = n3g;
     p.eqwall = (int)eq_walls(d);
     p.r_inner = d.r_inner; p.width = d.width; p.b = d.b;
     scales(d, p.dt, p.s);
     e = launch_geometry(g.ptr, p, B->stream);
-    const long count = (long)NGEO * d.n1 * n3g;
+    const long count = (long)NGEO * d.n1 * n2g * n3g;
     if (e == hipSuccess) e = hipMalloc(&g.fptr, sizeof(float) * count);
     if (e == hipSuccess) e = launch_geo_to_f32(g.ptr, g.fptr, count, B->stream);
     if (e != hipSuccess) {
@@ -664,7 +698,8 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
         h.N = d.n1 * h.P;
         h.n3p = x3_pitch(d.n3);
         h.Pp = d.n2 * h.n3p;
-        h.n3g = d.kind == MLBM_ELLIPSOID ? d.n3 : 1;
+        h.n3g = ellipsoidal(d.kind) ? d.n3 : 1;
+        h.n2g = d.kind == MLBM_ELLIPSOID_FULL ? d.n2 : 1;
         h.n3_magic = ((1ull << 40) + (uint64_t)h.n3p - 1) / (uint64_t)h.n3p;
         h.omega = 1.0 / d.tau;
         h.kappa = d.forcing_mode == MLBM_FORCING_IMPROVED ? 1.0 - 1.0 / (2.0 * d.tau) : 0.0;
@@ -917,6 +952,7 @@ mlbm_status mlbm_batch_run_until(mlbm_batch b, double tol, int64_t max_steps, in
     for (size_t i = 0; i < B->inst.size(); ++i) {
         start[i] = B->inst[i].t;
         if (B->inst[i].active) B->inst[i].status = -1;
+        else if (B->inst[i].status < 0) B->inst[i].status = 3;   // retired by the caller
     }
     std::vector<WindowState> ws;
     bool any_unstable = false;
@@ -958,18 +994,31 @@ mlbm_status mlbm_batch_run_until(mlbm_batch b, double tol, int64_t max_steps, in
         if (residual) residual[i] = ws.empty() ? -1.0 : ws[i].residual;
         if (status) status[i] = B->inst[i].status;
     }
-    // Every instance stopped on a window boundary, so every step count is a
-    // multiple of the even K and all instances share the buffer parity of the
-    // batch clock: they can all be stepped again together.
-    int64_t tmax = 0;
-    for (auto &I : B->inst) {
-        I.active = true;
-        tmax = std::max(tmax, I.t);
+    if (!B->keep_retired) {
+        mlbm_status s = reactivate_all(B);
+        if (s != MLBM_OK) return s;
     }
-    B->t = tmax;
-    mlbm_status s = build_tiles(B);
-    if (s != MLBM_OK) return s;
     return any_unstable ? fail(MLBM_E_UNSTABLE, "an instance became unstable") : MLBM_OK;
+}
+
+mlbm_status mlbm_batch_keep_retired(mlbm_batch b, int on)
+{
+    if (!b) return fail(MLBM_E_ARG, "null batch");
+    b->b->keep_retired = on != 0;
+    return on ? MLBM_OK : reactivate_all(b->b);
+}
+
+mlbm_status mlbm_batch_retire(mlbm_batch b, int i)
+{
+    if (!b || i < 0 || i >= (int)b->b->inst.size()) return fail(MLBM_E_ARG, "null batch or index out of range");
+    Batch *B = b->b;
+    if (B->t % B->K) return fail(MLBM_E_STATE, "instances retire between windows only (step count a multiple of check_every)");
+    if (!B->keep_retired) return fail(MLBM_E_STATE, "retiring needs mlbm_batch_keep_retired(b, 1)");
+    Instance &I = B->inst[i];
+    if (!I.active) return MLBM_OK;
+    I.active = false;
+    I.status = 3;
+    return build_tiles(B);
 }
 
 mlbm_status mlbm_run_until(mlbm_handle h, double tol, int64_t max_steps, int64_t *steps_taken)

@@ -16,16 +16,17 @@ namespace mlbm {
 
 __global__ void geometry_kernel(double *geo, GeoParams p)
 {
-    const int NX = p.n1 * p.n3g;
+    const int NX = p.n1 * p.n2g * p.n3g;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= NX) return;
-    const int x1 = idx / p.n3g, x3 = idx - x1 * p.n3g;
+    const int x1 = idx / (p.n2g * p.n3g), rem = idx - x1 * p.n2g * p.n3g;
+    const int x2 = rem / p.n3g, x3 = rem - x2 * p.n3g;
     const double dt = p.dt;
     // nodes cell centred between halfway walls, or on r_i + x1 Dr whose first
     // and last are the wall nodes of equilibrium walls (Sec. III)
     const double o1 = p.eqwall ? 0.0 : 0.5;
     double X1, X3;
-    double g11 = 1.0, g22 = 1.0, g33 = 1.0;
+    double g11 = 1.0, g22 = 1.0, g33 = 1.0, g12 = 0.0, g13 = 0.0, g23 = 0.0;
     double G[3][3][3] = {};
     if (p.kind == 0) {                        // flat
         X1 = (x1 + o1) * dt * p.s[0];
@@ -37,14 +38,25 @@ __global__ void geometry_kernel(double *geo, GeoParams p)
         g22 = r * r;
         G[0][1][1] = -r;                      // Gamma^r_{theta theta}
         G[1][0][1] = G[1][1][0] = 1.0 / r;    // Gamma^theta_{r theta}
-    } else {                                  // ellipsoid (r, theta, phi), a = c = 1, theta = 0
+    } else {                                  // ellipsoid (r, theta, phi), a = c = 1
         const double r = p.r_inner + (x1 + o1) * dt * p.s[0];
         const double ph = (x3 + 0.5 - 0.5 * p.n3) * dt * p.s[2];
-        const double cp = cos(ph), sp = sin(ph);
+        const double cp = cos(ph), sp = sin(ph), b2 = p.b * p.b;
         X1 = r;
         X3 = ph;
-        g22 = r * r * p.b * p.b * cp * cp;
-        g33 = r * r;
+        if (p.kind == 3) {                    // the metric at the node's theta (sector centred on 0)
+            const double th = (x2 + 0.5 - 0.5 * p.n2) * dt * p.s[1];
+            const double ct = cos(th), st = sin(th);
+            g11 = sp * sp + cp * cp * (ct * ct + b2 * st * st);
+            g22 = r * r * cp * cp * (st * st + b2 * ct * ct);
+            g33 = r * r * (cp * cp + sp * sp * (ct * ct + b2 * st * st));
+            g12 = r * (b2 - 1.0) * cp * cp * ct * st;
+            g13 = r * (1.0 - b2) * st * st * cp * sp;
+            g23 = r * r * (1.0 - b2) * cp * sp * ct * st;
+        } else {                              // frozen at theta = 0
+            g22 = r * r * b2 * cp * cp;
+            g33 = r * r;
+        }
         G[0][1][1] = -r * cp * cp;                    // Gamma^r_{theta theta}
         G[0][2][2] = -r;                              // Gamma^r_{phi phi}
         G[1][0][1] = G[1][1][0] = 1.0 / r;            // Gamma^theta_{r theta}
@@ -53,13 +65,27 @@ __global__ void geometry_kernel(double *geo, GeoParams p)
         G[2][1][1] = sp * cp;                         // Gamma^phi_{theta theta}
     }
     const double *s = p.s;
-    const double gi[3] = {1.0 / g11, 1.0 / g22, 1.0 / g33};
+    // inverse metric: reciprocals where it is diagonal, cofactors where it is
+    // not (the full ellipsoid off theta = 0)
+    double gi[3][3] = {{1.0 / g11, 0.0, 0.0}, {0.0, 1.0 / g22, 0.0}, {0.0, 0.0, 1.0 / g33}};
+    double det = g11 * g22 * g33;
+    if (g12 != 0.0 || g13 != 0.0 || g23 != 0.0) {
+        const double c11 = g22 * g33 - g23 * g23, c12 = g13 * g23 - g12 * g33, c13 = g12 * g23 - g13 * g22;
+        const double c22 = g11 * g33 - g13 * g13, c23 = g12 * g13 - g11 * g23, c33 = g11 * g22 - g12 * g12;
+        det = g11 * c11 + g12 * c12 + g13 * c13;
+        const double inv[3][3] = {{c11 / det, c12 / det, c13 / det}, {c12 / det, c22 / det, c23 / det},
+                                  {c13 / det, c23 / det, c33 / det}};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) gi[i][j] = inv[i][j];
+    }
     double *o = geo + idx;
     auto put = [&](int field, double v) { o[(size_t)field * NX] = v; };
-    put(G_D11, gi[0] / (s[0] * s[0]) - 1.0);
-    put(G_D22, gi[1] / (s[1] * s[1]) - 1.0);
-    put(G_D33, gi[2] / (s[2] * s[2]) - 1.0);
-    put(G_D12, 0.0); put(G_D13, 0.0); put(G_D23, 0.0);
+    put(G_D11, gi[0][0] / (s[0] * s[0]) - 1.0);
+    put(G_D22, gi[1][1] / (s[1] * s[1]) - 1.0);
+    put(G_D33, gi[2][2] / (s[2] * s[2]) - 1.0);
+    put(G_D12, gi[0][1] / (s[0] * s[1]));
+    put(G_D13, gi[0][2] / (s[0] * s[2]));
+    put(G_D23, gi[1][2] / (s[1] * s[2]));
     for (int i = 0; i < 3; ++i) {
         const int jk[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
         for (int e = 0; e < 6; ++e) {
@@ -67,10 +93,11 @@ __global__ void geometry_kernel(double *geo, GeoParams p)
             put(G_1_11 + 6 * i + e, dt * G[i][j][k] * s[j] * s[k] / s[i]);
         }
     }
-    put(G_F1, 0.0);
-    put(G_F2, dt * gi[1] / s[1]);
-    put(G_F3, 0.0);
-    put(G_SQRTG, sqrt(g11 * g22 * g33) * s[0] * s[1] * s[2]);
+    // covariant theta force K: contravariant g^{i theta} K (lattice units, per unit K)
+    put(G_F1, dt * gi[0][1] / s[0]);
+    put(G_F2, dt * gi[1][1] / s[1]);
+    put(G_F3, dt * gi[2][1] / s[2]);
+    put(G_SQRTG, sqrt(det) * s[0] * s[1] * s[2]);
     put(G_X1, X1);
     put(G_X3, X3);
 }
@@ -90,7 +117,7 @@ hipError_t launch_geo_to_f32(const double *geo, float *geof, long count, hipStre
 
 hipError_t launch_geometry(double *geo, const GeoParams &p, hipStream_t s)
 {
-    const int NX = p.n1 * p.n3g;
+    const int NX = p.n1 * p.n2g * p.n3g;
     hipLaunchKernelGGL(geometry_kernel, dim3((NX + 255) / 256), dim3(256), 0, s, geo, p);
     return hipGetLastError();
 }
@@ -103,9 +130,9 @@ hipError_t launch_geometry(double *geo, const GeoParams &p, hipStream_t s)
 // state: rho' = 1/sqrt(g), contravariant velocity init_u / s (or rest).
 __device__ void init_offsets(const InstDesc &d, int n, const double *init_u, double (&g)[Q])
 {
-    const int x1 = n / d.P, col = n - x1 * d.P, x3 = col % d.n3;
-    const int NX = d.n1 * d.n3g;
-    const int gi = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
+    const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
+    const int NX = geo_stride(d);
+    const int gi = geo_index(d, x1, x2, x3);
     const double *geo = d.geo;
     double D[3][3];
     D[0][0] = geo[G_D11 * NX + gi]; D[1][1] = geo[G_D22 * NX + gi]; D[2][2] = geo[G_D33 * NX + gi];
@@ -322,8 +349,8 @@ __global__ void moments_kernel(const InstDesc *dd, int parity, double *rho, doub
     double r, U[3];
     moments_only<double>(g, r, U);
     if (d.eqwall && (x1 == 0 || x1 == d.n1 - 1)) U[0] = U[1] = U[2] = 0.0;   // Dirichlet value
-    const int NX = d.n1 * d.n3g;
-    const int gi = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
+    const int NX = geo_stride(d);
+    const int gi = geo_index(d, x1, x2, x3);
     if (rho) rho[n] = r * d.geo[G_SQRTG * NX + gi];
     if (u)
         for (int i = 0; i < 3; ++i) u[(size_t)i * d.N + n] = d.s[i] * U[i];
@@ -377,9 +404,8 @@ __global__ void vortex_kernel(InstDesc d, int kind, double b, double h1, double 
     double vs = 0.0, os = 0.0, as = 0.0;
     if (n < d.N) {
         const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
-        (void)x2;
-        const int NX = d.n1 * d.n3g;
-        const int gi = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
+        const int NX = geo_stride(d);
+        const int gi = geo_index(d, x1, x2, x3);
         const double r = d.geo[G_X1 * NX + gi], ph = d.geo[G_X3 * NX + gi];
         const double *ur = u + n, *uz = u + 2 * (size_t)d.N + n;
         const double d3ur = ddx_axis(ur, 1, x3, d.n3, (d.walls & 4) ? 1 : 0, h3);
@@ -390,7 +416,7 @@ __global__ void vortex_kernel(InstDesc d, int kind, double b, double h1, double 
         const double uth = u[(size_t)d.N + n];
         double wv = 1.0, wo = 1.0, ws = 1.0;
         if (kind == 1) { wv = r; wo = r; }
-        else if (kind == 2) { const double cp = cos(ph); wv = r * r * b * cp; wo = r * b * cp; ws = r; }
+        else if (kind >= 2) { const double cp = cos(ph); wv = r * r * b * cp; wo = r * b * cp; ws = r; }
         vs = tw * uth * wv * h1 * h3;
         os = tw * vort * wo * h1 * h3;
         as = tw * ws * h1 * h3;
@@ -517,7 +543,7 @@ __global__ void step_nodes_kernel(const InstDesc *dd, int parity, const int64_t 
     typename Codec<ST>::G g[Q];
     gather_general<ST>(d.f[parity], d, x1, x2, x3, RefRow{d.ref}, g);
     NodeGeo<PAT, C> geo;
-    geo.load(d.geo, d.geof, x1 * d.n3g + (d.n3g > 1 ? x3 : 0), d.n1 * d.n3g, (C)d.force);
+    geo.load(d.geo, d.geof, geo_index(d, x1, x2, x3), geo_stride(d), (C)d.force);
     C rho, u[3];
     if (d.eqwall && (x1 == 0 || x1 == d.n1 - 1))
         wall_equilibrium<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, rho);

@@ -10,10 +10,11 @@
 //                values are offsets from the lattice weights: g = f - w_q
 //                for FP64/FP32, d = f / w_q - 1 - r for FP16/BF16 (r: the
 //                row's reference offset of the population).
-//   geometry     FP64, structure of arrays [NGEO][n1][n3g] over the cross
-//                section (n3g = 1 when nothing depends on x3, e.g. the
-//                cylinder): Delta^ij = g^ij - delta^ij, Christoffels, unit
-//                force, sqrt(g) and coordinates.  Read through L2.
+//   geometry     FP64, structure of arrays [NGEO][n1][n2g][n3g] (n3g = 1
+//                when nothing depends on x3, e.g. the cylinder; n2g = n2 only
+//                for the full ellipsoid, whose metric depends on theta):
+//                Delta^ij = g^ij - delta^ij, Christoffels, unit force,
+//                sqrt(g) and coordinates.  Read through L2.
 //   usnap        FP64 [3][N], lattice velocity at the previous check.
 #pragma once
 
@@ -56,6 +57,7 @@ struct InstDesc {
     int P, N;              // n2*n3, n1*n2*n3 (node count; node n = (x1*n2 + x2)*n3 + x3)
     int n3p, Pp;           // storage pitch of x3 (n3 rounded up to 16) and of a plane (n2*n3p)
     int n3g;               // 1 or n3
+    int n2g;               // 1, or n2 when the metric depends on theta (full ellipsoid)
     int tpr;               // tiles per x1 row (over the Pp storage columns)
     uint64_t n3_magic;     // ceil(2^40 / n3p): col / n3p = (col * magic) >> 40 for storage columns
     double omega;          // 1 / tau

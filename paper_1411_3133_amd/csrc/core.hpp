@@ -58,6 +58,13 @@ template <int PAT> struct Mask {
     static constexpr bool F(int i) { return PAT == PAT_GEN ? true : i == 1; }
 };
 
+// Geometry index of node (x1, x2, x3) and the stride of a geometry field.
+__host__ __device__ __forceinline__ int geo_index(const InstDesc &d, int x1, int x2, int x3)
+{
+    return (x1 * d.n2g + (d.n2g > 1 ? x2 : 0)) * d.n3g + (d.n3g > 1 ? x3 : 0);
+}
+__host__ __device__ __forceinline__ int geo_stride(const InstDesc &d) { return d.n1 * d.n2g * d.n3g; }
+
 constexpr int d_field(int i, int j)
 {
     int a = i < j ? i : j, b = i < j ? j : i;

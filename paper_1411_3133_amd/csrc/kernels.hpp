@@ -22,7 +22,7 @@ hipError_t launch_step_eq(const StepArgs &a, int pat, int st, bool check, int gr
 
 // geometry of one instance (FP64, on the device)
 struct GeoParams {
-    int kind, n1, n3, n3g;
+    int kind, n1, n2, n3, n2g, n3g;
     int eqwall;    // node placement of equilibrium walls (wall nodes at r_i, r_o)
     double r_inner, width, b, dt, s[3];
 };

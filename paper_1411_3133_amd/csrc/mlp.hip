@@ -275,7 +275,7 @@ __device__ void node_geo(const CaseGeo &c, int x1, int x3, double &sq2, double &
     const double o1 = c.eqwall ? 0.0 : 0.5;
     const double r = c.kind == MLBM_FLAT ? (x1 + o1) * dt : c.r_inner + (x1 + o1) * dt;
     sq2 = 1.0; sq3 = 1.0;
-    if (c.kind == MLBM_ELLIPSOID) {
+    if (c.kind == MLBM_ELLIPSOID || c.kind == MLBM_ELLIPSOID_FULL) {
         const double ph = (x3 + 0.5 - 0.5 * c.n3) * dt * c.s3;
         sq2 = r * c.b * cos(ph);
         sq3 = r;
@@ -343,8 +343,9 @@ CaseGeo case_geo(const mlbm_desc &d, double De, double R1_d, double R2_d)
     c.kind = d.kind; c.n1 = d.n1; c.n2 = d.n2; c.n3 = d.n3;
     c.eqwall = (d.walls & MLBM_WALL_EQUILIBRIUM) ? 1 : 0;
     c.r_inner = d.r_inner; c.width = d.width; c.b = d.b;
-    c.s2 = d.kind == MLBM_ELLIPSOID ? 1.0 / (d.b * d.r_inner) : 1.0;
-    c.s3 = d.kind == MLBM_ELLIPSOID ? 1.0 / d.r_inner : 1.0;
+    const bool ell = d.kind == MLBM_ELLIPSOID || d.kind == MLBM_ELLIPSOID_FULL;
+    c.s2 = ell ? 1.0 / (d.b * d.r_inner) : 1.0;
+    c.s3 = ell ? 1.0 / d.r_inner : 1.0;
     c.f0 = De / 100.0;
     c.f1 = R1_d / 20.0;
     c.f2 = (R1_d > 0.0 && R2_d > 0.0) ? std::log(R2_d / R1_d) / std::log(4.0) : 0.0;

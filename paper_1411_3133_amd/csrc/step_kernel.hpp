@@ -93,9 +93,11 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
             } else {
                 gather_general<ST>(src, d, x1, x2, x3, R, g);
             }
-            const int gidx = x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
+            // per cross-section geometry; only the general pattern may depend on theta
+            const int gidx = PAT == PAT_GEN ? geo_index(d, x1, x2, x3) : x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
+            const int gstride = PAT == PAT_GEN ? geo_stride(d) : d.n1 * d.n3g;
             NodeGeo<PAT, C> geo;
-            geo.load(d.geo, d.geof, gidx, d.n1 * d.n3g, (C)d.force);
+            geo.load(d.geo, d.geof, gidx, gstride, (C)d.force);
             C rho, u[3];
             if (eq_row) {
                 wall_equilibrium<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, rho);

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmlbm.so")
 Q = 41
 
 OK, E_ARG, E_HIP, E_OOM, E_UNSTABLE, E_STATE, E_IO = range(7)
-KIND = {"flat": 0, "cylinder": 1, "ellipsoid": 2}
+KIND = {"flat": 0, "cylinder": 1, "ellipsoid": 2, "ellipsoid_full": 3}
 PRECISION = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3, "f32c64": 4}
 
 
@@ -38,7 +38,7 @@ class Desc(C.Structure):
         ("tau", C.c_double), ("force", C.c_double),
         ("init_u", C.POINTER(C.c_double)),
         ("target_De", C.c_double), ("perturb_amp", C.c_double), ("seed", C.c_uint64),
-        ("init_u_xsec", C.c_int32), ("reserved", C.c_int32),
+        ("init_u_xsec", C.c_int32), ("reserved", C.c_int32), ("dtheta", C.c_double),
     ]
 
 
@@ -49,6 +49,7 @@ EXPORTS = [
     "mlbm_time", "mlbm_pull_map", "mlbm_save", "mlbm_load", "mlbm_destroy", "mlbm_last_error", "mlbm_lattice",
     "mlbm_batch_create", "mlbm_batch_step", "mlbm_batch_run_until", "mlbm_batch_get",
     "mlbm_batch_set_launch", "mlbm_batch_autotune", "mlbm_batch_use_graph",
+    "mlbm_batch_keep_retired", "mlbm_batch_retire",
     "mlbm_batch_last_step_ms", "mlbm_batch_size", "mlbm_batch_destroy",
     "mlbm_net_num_params", "mlbm_net_create", "mlbm_net_destroy", "mlbm_net_last_error",
     "mlbm_net_params", "mlbm_net_forward", "mlbm_net_gradient", "mlbm_net_adam_step",
@@ -103,6 +104,8 @@ def load():
     L.mlbm_batch_set_launch.argtypes = [vp, C.c_int, C.c_int]
     L.mlbm_batch_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     L.mlbm_batch_use_graph.argtypes = [vp, C.c_int]
+    L.mlbm_batch_keep_retired.argtypes = [vp, C.c_int]
+    L.mlbm_batch_retire.argtypes = [vp, C.c_int]
     L.mlbm_batch_last_step_ms.argtypes = [vp]
     L.mlbm_batch_last_step_ms.restype = C.c_double
     L.mlbm_batch_size.argtypes = [vp]
@@ -160,7 +163,7 @@ def make_desc(case: Case, init_u: Optional[np.ndarray] = None, start: Optional[d
     d = Desc(kind=KIND[case.kind], n1=case.n1, n2=case.n2, n3=case.n3, walls=case.walls,
              forcing_mode=case.forcing_mode, precision=PRECISION[case.precision],
              check_every=case.check_every, r_inner=case.r_inner, width=case.width, b=case.b,
-             tau=case.tau, force=case.force, init_u=None)
+             tau=case.tau, force=case.force, init_u=None, dtheta=case.dtheta)
     if start:
         if start.get("target_De"):
             d.target_De = float(start["target_De"])
@@ -366,6 +369,14 @@ class Batch:
 
     def use_graph(self, on: bool):
         _check(load().mlbm_batch_use_graph(self._h, 1 if on else 0))
+
+    def keep_retired(self, on: bool):
+        """Keep retired instances out of later steps (True) or bring every
+        instance back (False)."""
+        _check(load().mlbm_batch_keep_retired(self._h, 1 if on else 0))
+
+    def retire(self, i: int):
+        _check(load().mlbm_batch_retire(self._h, int(i)))
 
 
 def _net_check(status):

@@ -5,14 +5,16 @@ smallest De whose steady state shows at least k cells (cell counting: see
 warmstart.cell_count). Round 0 runs a grid of De values of every pair in one
 batch; every later round runs the midpoints of all open brackets in one
 batch, until each bracket is narrower than `rel_width` of its upper end.
-Runs start from the laminar profile with a seeded 1e-4 perturbation, or from
-the warm-start network trained on the round-0 fields (plain start as
-fallback). Orchestration only: every step runs in libmlbm's kernels.
+Runs start from the laminar profile with a seeded 1e-4 perturbation, or --
+every round of a warm sweep, its first included -- from the prediction of a
+warm-start network trained beforehand (for instance on the steady fields of
+a plain sweep's first round), with the plain start as fallback where a warm
+run stalls. Orchestration only: every step runs in libmlbm's kernels.
 """
 from __future__ import annotations
 
 import time
-from typing import Callable, Dict, Sequence, Tuple
+from typing import Callable, Dict, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -22,17 +24,34 @@ from .mlbm import Net
 
 
 def _run(cases, inits_plain, tol, max_steps, net=None, fallback_after=None, log=None):
-    """Fields, steps, status and observables (<omega>, <v_theta>, measured De)
-    of a batch of cases."""
+    """Fields, steps, status, observables (<omega>, <v_theta>, measured De),
+    seconds and the indices of runs that fell back to the plain start, of a
+    batch of cases."""
     if net is None:
         b, steps, status, secs = W.run_to_steady(cases, inits_plain, tol, max_steps, log=log)
         fields = [b[i].moments() for i in range(len(cases))]
         obs = [b[i].vortex_intensity() for i in range(len(cases))]
         b.close()
-        return fields, steps, status, obs, secs
-    fields, steps, status, secs, _, _, _, obs = W.warm_start_run(net, cases, inits_plain, tol, max_steps,
-                                                                 fallback_after, log)
-    return fields, steps, status, obs, secs
+        return fields, steps, status, obs, secs, []
+    fields, steps, status, secs, _, redo, _, obs = W.warm_start_run(net, cases, inits_plain, tol, max_steps,
+                                                                    fallback_after, log)
+    return fields, steps, status, obs, secs, list(redo)
+
+
+def even_grid(lo: float, hi: float, points: int):
+    """`points` De values from lo to hi, evenly spaced (rounded to 0.01)."""
+    return [round(lo + (hi - lo) * k / (points - 1), 2) for k in range(points)]
+
+
+def train_on(dataset, net_shape=(64, 3), train_steps=((8000, 2e-3), (6000, 5e-4), (3000, 1e-4))):
+    """A warm-start network trained on [(case, u)] steady fields."""
+    net = Net(net_shape[0], net_shape[1], K.net_init_params(net_shape[0], net_shape[1], seed=3))
+    for c, u in dataset:
+        De, R1, R2, U = W.case_params(c)
+        net.dataset_add(c, u, De, R1, R2, U)
+    for k, (n, lr) in enumerate(train_steps):
+        net.train(n, batch=4096, lr=lr, seed=k + 1)
+    return net
 
 
 def knee(De: Sequence[float], omega: Sequence[float]):
@@ -62,44 +81,40 @@ def knee(De: Sequence[float], omega: Sequence[float]):
     return None if best is None else best[1]
 
 
-def critical_dean(pairs: Sequence[Tuple[str, Callable[[float], K.Case]]], De_grid: Sequence[float],
-                  ks: Sequence[int] = (2, 4, 6), rel_width: float = 0.01, tol: float = 1e-6,
-                  max_steps: int = 200000, seed: int = 7, warm: bool = False, net_shape=(64, 3),
-                  train_steps=((8000, 2e-3), (6000, 5e-4), (3000, 1e-4)), fallback_after: int = 60000,
-                  log=None) -> Dict:
-    """Bracket the onset De of k cells for every pair; returns brackets of
-    nominal and measured De per (pair, k), the onset read off each pair's
-    <omega>(measured De) curve of converged runs (`knee`), the cell counts
-    and <omega> seen, and wall time and instance-steps per round."""
+def critical_dean(pairs: Sequence[Tuple], De_grid, ks: Sequence[int] = (2, 4, 6), rel_width: float = 0.01,
+                  tol: float = 1e-6, max_steps: int = 200000, seed: int = 7, net: Optional[Net] = None,
+                  fallback_after: int = 60000, log=None) -> Dict:
+    """Bracket the onset De of k cells for every pair ((name, make) or
+    (name, make, De_top)); De_grid is one sequence of De for every pair, or a
+    callable De_top -> sequence. With `net` every run starts from its
+    prediction (plain start as fallback where a warm run stalls). Returns
+    brackets of nominal and measured De per (pair, k), the onset read off
+    each pair's <omega>(measured De) curve of converged runs (`knee`), the
+    cell counts and <omega> seen, wall time, instance-steps and fallbacks
+    per round, whether each run finished from the warm start, and the
+    converged first-round fields as a training set ([(case, u)])."""
     t_all = time.perf_counter()
-    # (pair, De_nom) -> (cells, De_meas, status, <omega>)
-    seen: Dict[Tuple[str, float], Tuple[int, float, int, float]] = {}
+    # (pair, De_nom) -> (cells, De_meas, status, <omega>, finished from the warm start)
+    seen: Dict[Tuple[str, float], Tuple[int, float, int, float, bool]] = {}
     rounds = []
 
-    def run_round(items, net=None):
+    def run_round(items):
         cases = [make(De) for (_, make, De) in items]
         plain = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
-        fields, steps, status, obs, secs = _run(cases, plain, tol, max_steps, net, fallback_after, log)
-        for (name, _, De), c, (_, u), st, ob in zip(items, cases, fields, status, obs):
-            seen[(name, De)] = (W.cell_count(c, u), float(ob[2]), int(st), float(ob[0]))
+        fields, steps, status, obs, secs, redo = _run(cases, plain, tol, max_steps, net, fallback_after, log)
+        for j, ((name, _, De), c, (_, u), st, ob) in enumerate(zip(items, cases, fields, status, obs)):
+            seen[(name, De)] = (W.cell_count(c, u), float(ob[2]), int(st), float(ob[0]),
+                                net is not None and j not in redo)
         rounds.append({"instances": len(items), "seconds": round(secs, 3), "instance_steps": int(np.sum(steps)),
-                       "converged": int(np.sum(status == 0)), "unstable": int(np.sum(status == 2))})
+                       "converged": int(np.sum(status == 0)), "unstable": int(np.sum(status == 2)),
+                       "fallbacks": len(redo)})
         return cases, fields, status
 
-    grid = [(name, make, float(De)) for name, make in pairs for De in De_grid]
+    pairs = [(p[0], p[1], p[2] if len(p) > 2 else None) for p in pairs]
+    grid = [(name, make, float(De)) for name, make, top in pairs
+            for De in (De_grid(top) if callable(De_grid) else De_grid)]
     cases0, fields0, status0 = run_round(grid)
-    net = None
-    t_train = 0.0
-    if warm:
-        t0 = time.perf_counter()
-        net = Net(net_shape[0], net_shape[1], K.net_init_params(net_shape[0], net_shape[1], seed=3))
-        for c, (_, u), st in zip(cases0, fields0, status0):
-            if st == 0 and np.all(np.isfinite(u)):
-                De, R1, R2, U = W.case_params(c)
-                net.dataset_add(c, u, De, R1, R2, U)
-        for k, (n, lr) in enumerate(train_steps):
-            net.train(n, batch=4096, lr=lr, seed=k + 1)
-        t_train = time.perf_counter() - t0
+    dataset = [(c, u) for c, (_, u), st in zip(cases0, fields0, status0) if st == 0 and np.all(np.isfinite(u))]
 
     def bracket(name, k):
         des = sorted(De for (n, De) in seen if n == name)
@@ -109,10 +124,10 @@ def critical_dean(pairs: Sequence[Tuple[str, Callable[[float], K.Case]]], De_gri
                 return (des[i - 1], des[i]) if i > 0 else (None, des[i])
         return (des[-1], None)
 
-    makers = dict(pairs)
+    makers = {name: make for name, make, _ in pairs}
     while True:
         todo = {}
-        for name, _ in pairs:
+        for name, _, _ in pairs:
             for k in ks:
                 lo, hi = bracket(name, k)
                 if lo is None or hi is None or (hi - lo) <= rel_width * hi:
@@ -123,10 +138,10 @@ def critical_dean(pairs: Sequence[Tuple[str, Callable[[float], K.Case]]], De_gri
             break
         if log:
             log(f"bisection round {len(rounds)}: {len(todo)} instances")
-        run_round(list(todo.values()), net)
+        run_round(list(todo.values()))
 
     out = {}
-    for name, _ in pairs:
+    for name, _, _ in pairs:
         for k in ks:
             lo, hi = bracket(name, k)
             out[f"{name}/k{k}"] = {
@@ -135,12 +150,17 @@ def critical_dean(pairs: Sequence[Tuple[str, Callable[[float], K.Case]]], De_gri
                                 seen[(name, hi)][1] if hi is not None else None],
                 "status_at_ends": [seen[(name, lo)][2] if lo is not None else None,
                                    seen[(name, hi)][2] if hi is not None else None],
+                "warm_at_ends": [seen[(name, lo)][4] if lo is not None else None,
+                                 seen[(name, hi)][4] if hi is not None else None],
             }
     knees = {}
-    for name, _ in pairs:
+    for name, _, _ in pairs:
         pts = [(v[1], v[3]) for (n, _), v in seen.items() if n == name and v[2] == 0]
         knees[name] = knee([p[0] for p in pts], [p[1] for p in pts]) if len(pts) >= 4 else None
-    return {"onsets": out, "knees": knees, "rounds": rounds, "train_seconds": round(t_train, 2),
+    return {"onsets": out, "knees": knees, "rounds": rounds,
             "seconds": round(time.perf_counter() - t_all, 2),
+            "De_top": {name: top for name, _, top in pairs},
             "cells": {f"{n}@{De:g}": v[0] for (n, De), v in sorted(seen.items())},
-            "omega": {f"{n}@{De:g}": v[3] for (n, De), v in sorted(seen.items())}}
+            "omega": {f"{n}@{De:g}": v[3] for (n, De), v in sorted(seen.items())},
+            "finished_warm": {f"{n}@{De:g}": v[4] for (n, De), v in sorted(seen.items())},
+            "dataset": dataset}

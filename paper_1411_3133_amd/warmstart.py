@@ -28,16 +28,24 @@ def case_params(case: K.Case):
 
 
 def run_to_steady(cases: Sequence[K.Case], inits, tol: float, max_steps: int, chunk: int = 20000,
-                  log=None, stream=None):
+                  log=None, stream=None, stall_chunks: Optional[int] = None, stall_factor: float = 0.8):
     """Batched run to residual <= tol; returns (batch, steps, status, seconds).
-    status: 0 converged, 1 step cap, 2 unstable. The time includes creating
-    the batch (geometry and initial populations)."""
+    status: 0 converged, 1 step cap, 2 unstable, 3 stalled. Converged and
+    unstable instances leave the batch at once and are not stepped again.
+    With stall_chunks, an instance whose residual has not fallen below
+    stall_factor times its best value for that many chunks (and is still
+    above 10 tol) is retired as stalled. The time includes creating the
+    batch (geometry and initial populations); on return every instance is
+    back in the batch, in the state it stopped in."""
     t0 = time.perf_counter()
     b = Batch(cases, inits, stream=stream)
+    b.keep_retired(True)
     n = len(cases)
     steps = np.zeros(n, np.int64)
     status = np.full(n, 1, np.int32)
     done = np.zeros(n, bool)
+    best = np.full(n, np.inf)
+    since = np.zeros(n, np.int64)
     total = 0
     while total < max_steps and not done.all():
         st, res, sta = b.run_until(tol, min(chunk, max_steps - total))
@@ -48,9 +56,21 @@ def run_to_steady(cases: Sequence[K.Case], inits, tol: float, max_steps: int, ch
                     done[i] = True
                     status[i] = sta[i]
         total += int(st.max())
+        if stall_chunks:
+            for i in np.flatnonzero(~done):
+                r = res[i]
+                if r >= 0.0 and r < stall_factor * best[i]:
+                    best[i], since[i] = r, 0
+                else:
+                    since[i] += 1
+                if since[i] >= stall_chunks and r > 10.0 * tol and total < max_steps:
+                    b.retire(int(i))
+                    done[i] = True
+                    status[i] = 3
         if log:
             log(f"  t={total} converged={int((status == 0).sum())} unstable={int((status == 2).sum())} "
-                f"elapsed={time.perf_counter() - t0:.1f}s")
+                f"stalled={int((status == 3).sum())} elapsed={time.perf_counter() - t0:.1f}s")
+    b.keep_retired(False)
     return b, steps, status, time.perf_counter() - t0
 
 
@@ -97,30 +117,32 @@ def cell_count(case: K.Case, u: np.ndarray, threshold: float = 0.1, floor: float
 
 
 def warm_start_run(net: Net, cases: Sequence[K.Case], plain_inits, tol: float, max_steps: int,
-                   fallback_after: Optional[int] = None, log=None):
-    """Batched run from the network's prediction. Instances that have not
-    reached tol after fallback_after steps are run again from their plain
-    start (the fallback) with the full max_steps, in a second batch; their
-    step count and the wall time include the abandoned warm phase. Returns
-    (fields, steps, status, seconds, inference_seconds, fallback_indices,
-    warm_init, observables): fields[i] = (rho, u), observables[i] =
-    (<omega>, <v_theta>, De) of the final state."""
+                   fallback_after: Optional[int] = None, log=None, stall_chunks: Optional[int] = 3,
+                   chunk: int = 5000):
+    """Batched run from the network's prediction. An instance whose residual
+    stalls (no 20 % fall below its best over stall_chunks chunks of `chunk`
+    steps) or that has not reached tol after fallback_after steps is run
+    again from its plain start (the fallback) with the full max_steps, in a
+    second batch; its step count and the wall time include the abandoned
+    warm phase. Returns (fields, steps, status, seconds, inference_seconds,
+    fallback_indices, warm_init, observables): fields[i] = (rho, u),
+    observables[i] = (<omega>, <v_theta>, De) of the final state."""
     t0 = time.perf_counter()
     warm_init = predict_inits(net, cases)
     t_inf = time.perf_counter() - t0
     budget = max_steps if fallback_after is None else min(fallback_after, max_steps)
-    bw, sw, stw, _ = run_to_steady(cases, warm_init, tol, budget, log=log)
+    bw, sw, stw, _ = run_to_steady(cases, warm_init, tol, budget, log=log, chunk=chunk, stall_chunks=stall_chunks)
     fields = [bw[i].moments() for i in range(len(cases))]
     obs = [bw[i].vortex_intensity() for i in range(len(cases))]
     bw.close()
-    redo = [i for i in range(len(cases)) if stw[i] != 0] if budget < max_steps else []
+    redo = [i for i in range(len(cases)) if stw[i] == 3 or (stw[i] != 0 and budget < max_steps)]
     if redo:
         if log:
             log(f"  fallback to the plain start for {len(redo)} case(s)")
         bf, sf, stf, _ = run_to_steady([cases[i] for i in redo], [plain_inits[i] for i in redo], tol,
                                        max_steps, log=log)
         for j, i in enumerate(redo):
-            sw[i] = budget + sf[j]
+            sw[i] = sw[i] + sf[j]          # the abandoned warm steps, then the plain run
             stw[i] = stf[j]
             fields[i] = bf[j].moments()
             obs[i] = bf[j].vortex_intensity()

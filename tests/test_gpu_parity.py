@@ -11,6 +11,7 @@ Tolerances
   sampled one-step checks bound each population by the storage rounding of
   its offset d = f / w - 1 (half an ulp of |d| <= 4: 2e-3 FP16, 1.6e-2 BF16,
   in units of w)."""
+import math
 import os
 
 import numpy as np
@@ -620,3 +621,61 @@ def test_warm_start_network_file_roundtrip(tmp_path):
     with pytest.raises(mlbm.MlbmError):
         (tmp_path / "bad.bin").write_bytes(b"MLBMNET1" + b"\x00" * 8)
         mlbm.Net.load_file(str(tmp_path / "bad.bin"))
+
+
+# --------------------------------------------------------------------------
+# the full double-curved geometry (metric at every node's theta)
+# --------------------------------------------------------------------------
+
+# theta spacing of Sec. IV B (the lattice metric stays near the identity);
+# small inner radii give theta sectors of +-0.34, +-0.67 and +-0.56 rad
+FULL_CASES = [
+    ("full-b2", K.Case(kind="ellipsoid_full", n1=8, n2=24, n3=8, walls=1, r_inner=3.0, width=1.0, b=math.sqrt(2.0),
+                       tau=0.8, force=1e-3)),
+    ("full-b07", K.Case(kind="ellipsoid_full", n1=8, n2=16, n3=10, walls=1, r_inner=2.0, width=1.0, b=0.7,
+                        tau=0.8, force=1e-3)),
+    ("full-eq", K.Case(kind="ellipsoid_full", n1=9, n2=30, n3=8, walls=K.WALL_AXIS1 | K.WALL_EQ, r_inner=2.5,
+                       width=1.0, b=1.3, tau=0.85, force=1e-3)),
+]
+
+
+@pytest.mark.parametrize("name,case", FULL_CASES, ids=[c[0] for c in FULL_CASES])
+@pytest.mark.parametrize("steps", [1, 40])
+def test_fp64_full_ellipsoid_matches_oracle(name, case, steps):
+    """The double-curved channel with the metric of Sec. IV evaluated at each
+    node's theta (non-diagonal, all 18 Christoffels, three force components;
+    theta sectors up to +-0.67 rad, periodic in theta), through the general
+    kernel: FP64 populations, moments and observables against the oracle."""
+    case = case.replace(precision="f64")
+    init = K.perturbed_start(case, seed=13, amp=0.05, U_nom=0.05, base="rest")
+    g = mlbm.Sim(case, init_u=init)
+    o = O.Sim(case, init_u=init)
+    assert _rel_max(g.get_f(), o.get_f()) < 1e-15
+    g.step(steps)
+    o.step(steps)
+    assert _rel_max(g.get_f(), o.get_f()) < 1e-13
+    rg, ug = g.moments()
+    ro, uo, _ = o.moments()
+    assert _rel_max(rg, ro) < 1e-13
+    assert np.abs(ug - uo).max() < 1e-12 * max(1.0, np.abs(uo).max())
+    og, vg, dg = g.vortex_intensity()
+    oo, vo, do = o.observables()
+    assert abs(vg - vo) <= 1e-11 * max(abs(vo), 1e-30)
+    assert abs(dg - do) <= 1e-11 * max(abs(do), 1e-30)
+    g.close()
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 1e-5), ("f16", 1e-3)])
+def test_full_ellipsoid_reduced_precision(prec, bound):
+    """FP32 and FP16 storage on the full double-curved geometry against the
+    FP64 oracle after 500 steps (velocity relative L2)."""
+    case = FULL_CASES[0][1]
+    init = K.perturbed_start(case, seed=14, amp=0.05, U_nom=0.05, base="rest")
+    o = O.Sim(case.replace(precision="f64"), init_u=init)
+    o.step(500)
+    g = mlbm.Sim(case.replace(precision=prec), init_u=init)
+    g.step(500)
+    err = _rel_l2(g.moments()[1], o.moments()[1])
+    print(f"full ellipsoid {prec}: velocity rel L2 {err:.3e}")
+    assert err < bound
+    g.close()

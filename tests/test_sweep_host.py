@@ -36,7 +36,8 @@ def fake_runs(monkeypatch):
             omega = 0.01 * max(0.0, De - 0.97 * th[2])     # vorticity rises linearly past the 2-cell onset
             obs.append((omega, 1.0, De))
         n = len(cases)
-        return fields, np.full(n, 1000), np.zeros(n, np.int32), obs, 0.01
+        redo = [0] if net is not None else []          # a warm sweep: its first instance falls back
+        return fields, np.full(n, 1000), np.zeros(n, np.int32), obs, 0.01, redo
 
     monkeypatch.setattr(sweep, "_run", fake_run)
     return calls
@@ -90,3 +91,21 @@ def test_knee_is_stable_under_small_noise_and_absent_without_a_rise():
     assert abs(sweep.knee(x, y) - 47.0) < 0.5
     assert sweep.knee(x, np.full(len(x), 0.3)) is None          # flat: no rising segment
     assert sweep.knee(x, 1.0 - 0.01 * x) is None                # falling throughout
+
+
+def test_per_pair_grids_warm_accounting_and_dataset(fake_runs):
+    """A callable grid gives each pair its own De range (up to its De_top);
+    a warm sweep records the fallbacks of every round and which runs finished
+    from the warm start; the converged first-round fields come back as a
+    training set."""
+    pairs = [("A", lambda De: K.ellipsoid_case(20.0, 30.0, 8, 2, 40, 0.6, De=De, label="A"), 60.0),
+             ("B", lambda De: K.ellipsoid_case(20.0, 30.0, 8, 2, 40, 0.6, De=De, label="B"), 70.0)]
+    r = sweep.critical_dean(pairs, lambda top: sweep.even_grid(20.0, top, 5), ks=(2,), rel_width=0.01,
+                            net=object())
+    assert fake_runs[0] == 10
+    assert max(float(k.split("@")[1]) for k in r["cells"] if k.startswith("A@")) <= 60.0
+    assert r["De_top"] == {"A": 60.0, "B": 70.0}
+    assert all(rd["fallbacks"] == 1 for rd in r["rounds"])
+    assert sum(1 for v in r["finished_warm"].values() if not v) == len(r["rounds"])
+    assert len(r["dataset"]) == 10
+    assert sweep.even_grid(20.0, 60.0, 5) == [20.0, 30.0, 40.0, 50.0, 60.0]
