@@ -263,11 +263,11 @@ mlbm_status mlbm_batch_run_until(mlbm_batch b, double tol, int64_t max_steps, in
 
 /* Retirement across calls.  By default mlbm_batch_run_until brings every
  * instance back when it returns.  With mlbm_batch_keep_retired(b, 1) the
- * instances it retired (converged, unstable, at their step cap) stay out of
- * later mlbm_batch_step / mlbm_batch_run_until calls, keeping their state
- * and step count, and mlbm_batch_retire(b, i) retires instance i at once
- * (its status then reads 3); mlbm_batch_keep_retired(b, 0) brings every
- * instance back.  Retiring needs the batch on a window boundary (a step
+ * instances it retired as converged or unstable stay out of later
+ * mlbm_batch_step / mlbm_batch_run_until calls, keeping their state and
+ * step count (those that only reached the call's max_steps come back), and
+ * mlbm_batch_retire(b, i) retires instance i at once (its status then reads
+ * 3); mlbm_batch_keep_retired(b, 0) brings every instance back.  Retiring needs the batch on a window boundary (a step
  * count that is a multiple of check_every; E_STATE otherwise). */
 mlbm_status mlbm_batch_keep_retired(mlbm_batch b, int on);
 mlbm_status mlbm_batch_retire(mlbm_batch b, int i);

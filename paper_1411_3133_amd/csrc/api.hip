@@ -524,18 +524,24 @@ mlbm_status advance(Batch *B, int64_t n)
 // Every instance stops on a window boundary, so every step count is a
 // multiple of the even K and all instances share the buffer parity of the
 // batch clock: they can all be stepped again together.
-mlbm_status reactivate_all(Batch *B)
+mlbm_status reactivate(Batch *B, bool capped_only)
 {
     bool changed = false;
     int64_t tmax = 0;
     for (auto &I : B->inst) {
-        changed |= !I.active;
-        I.active = true;
+        // capped_only: bring back the instances that stopped at the call's
+        // step cap; converged, unstable and caller-retired ones stay out
+        if (!I.active && (!capped_only || I.status == 1)) {
+            I.active = true;
+            changed = true;
+        }
         tmax = std::max(tmax, I.t);
     }
     B->t = tmax;
     return changed ? build_tiles(B) : MLBM_OK;
 }
+
+mlbm_status reactivate_all(Batch *B) { return reactivate(B, false); }
 
 mlbm_status read_ws(Batch *B, std::vector<WindowState> &ws)
 {
@@ -994,10 +1000,8 @@ mlbm_status mlbm_batch_run_until(mlbm_batch b, double tol, int64_t max_steps, in
         if (residual) residual[i] = ws.empty() ? -1.0 : ws[i].residual;
         if (status) status[i] = B->inst[i].status;
     }
-    if (!B->keep_retired) {
-        mlbm_status s = reactivate_all(B);
-        if (s != MLBM_OK) return s;
-    }
+    mlbm_status s = reactivate(B, B->keep_retired);
+    if (s != MLBM_OK) return s;
     return any_unstable ? fail(MLBM_E_UNSTABLE, "an instance became unstable") : MLBM_OK;
 }
 

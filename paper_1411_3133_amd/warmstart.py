@@ -55,6 +55,8 @@ def run_to_steady(cases: Sequence[K.Case], inits, tol: float, max_steps: int, ch
                 if sta[i] in (0, 2):
                     done[i] = True
                     status[i] = sta[i]
+        if int(st.max()) == 0:          # nothing left to step
+            break
         total += int(st.max())
         if stall_chunks:
             for i in np.flatnonzero(~done):
