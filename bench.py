@@ -263,6 +263,7 @@ def beyond_cache_leg(precision, steps=500, warmup=100, block=0, grid=0):
             "MLUPS": round(case.N * steps / wall / 1e6, 1),
             "achieved_GBs": round(alg / (ev_ms * 1e-3) / 1e9, 1),
             "frac": round(alg / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(f"ellipsoid_96x{case.n2}x192_{precision}", kernel_source_digest()),
             "health": health}
 
 

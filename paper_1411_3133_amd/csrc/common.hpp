@@ -95,6 +95,28 @@ __device__ __forceinline__ void gstore(void *base, uint64_t byte_off, T v)
     *(MLBM_GLOBAL T *)((MLBM_GLOBAL char *)base + byte_off) = v;
 }
 
+// Tables that no kernel writes while it runs (instance descriptors, the
+// tile queue, the 16-bit reference rows). Read through the constant address
+// space with a wavefront-uniform address they become scalar loads into
+// SGPRs. Read as plain global memory behind the kernel's own stores, the
+// compiler cannot prove them unchanged between loop iterations: it reloads
+// each field with a vector load and a wait where it is used, and carries the
+// arithmetic on it in VGPRs.
+#define MLBM_CONST __attribute__((address_space(4)))
+
+template <class T>
+__device__ __forceinline__ T load_uniform(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized records only");
+    uint32_t w[sizeof(T) / 4];
+    const MLBM_CONST uint32_t *s = (const MLBM_CONST uint32_t *)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = s[i];
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
+
 // Store that is not expected to be read again soon (streamed output).
 template <typename T>
 __device__ __forceinline__ void gstore_nt(void *base, uint64_t byte_off, T v)
@@ -211,6 +233,22 @@ template <> struct Codec<ST_F16> {
     static constexpr bool REF = true;
     static constexpr bool SCALED = true;
     __device__ static __forceinline__ C decode(T v, C r) { return f16_bits_to_float(v) + r; }
+    // decode with a wavefront-uniform r (a scalar register): one mixed-precision
+    // FMA, d * 1 + r with d read as binary16, instead of a conversion and an add
+    // (the same single rounding of d + r, so the same result)
+    __device__ static __forceinline__ C decode_uniform(T v, C r)
+    {
+        float x;
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(x) : "v"((uint32_t)v), "s"(r));
+        return x;
+    }
+    // the same with r chosen per lane (a vector register)
+    __device__ static __forceinline__ C decode_lane(T v, C r)
+    {
+        float x;
+        asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(x) : "v"((uint32_t)v), "v"(r));
+        return x;
+    }
     __device__ static __forceinline__ T encode(G h, C r) { return float_to_f16_bits(h - r); }
     __device__ static __forceinline__ T encode_sr(G h, C r, uint32_t rnd) { return float_to_f16_bits_sr(h - r, rnd); }
     __device__ static __forceinline__ double to_f64(T v, double w, double r)

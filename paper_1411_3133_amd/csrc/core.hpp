@@ -463,8 +463,8 @@ struct RoundBits {
 // RefScalar: for rows uniform across the wavefront (the step kernel's
 // gathers and store), read through the scalar cache; reads only.
 // RefRow: per-lane rows (auxiliary kernels).
-#define MLBM_CONST __attribute__((address_space(4)))
 struct RefScalar {
+    static constexpr bool UNIFORM = true;
     const float *ref;
     __device__ __forceinline__ float get_r(int, int row, int q) const
     {
@@ -472,9 +472,27 @@ struct RefScalar {
     }
 };
 struct RefRow {
+    static constexpr bool UNIFORM = false;
     const float *ref;
     __device__ __forceinline__ float get_r(int, int row, int q) const { return ref[row * Q + q]; }
 };
+
+// Decode of a pulled value; with the scalar reference view r is uniform
+// across the wavefront.
+template <int ST, class R>
+__device__ __forceinline__ typename Codec<ST>::C decode_wave(typename Codec<ST>::T v, typename Codec<ST>::C r)
+{
+    if constexpr (ST == ST_F16 && R::UNIFORM) return Codec<ST>::decode_uniform(v, r);
+    else return Codec<ST>::decode(v, r);
+}
+
+// Decode of a pulled value whose r was chosen per lane.
+template <int ST>
+__device__ __forceinline__ typename Codec<ST>::C decode_lane(typename Codec<ST>::T v, typename Codec<ST>::C r)
+{
+    if constexpr (ST == ST_F16) return Codec<ST>::decode_lane(v, r);
+    else return Codec<ST>::decode(v, r);
+}
 
 struct LaneOffsets {
     uint32_t o2[5], o3[5];
@@ -515,7 +533,42 @@ __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, 
         constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
         const void *rowp = (const char *)src + rb[cslot(c1)] + (uint64_t)q * PS;
         const C r = Codec<ST>::REF ? (C)ref.get_r(c1, rows[cslot(c1)], q) : C(0);
-        g[q] = Codec<ST>::decode(gload<T>(rowp, L.o2[cslot(c2)] + L.o3[cslot(c3)]), r);
+        g[q] = decode_wave<ST, R>(gload<T>(rowp, L.o2[cslot(c2)] + L.o3[cslot(c3)]), r);
+    });
+}
+
+// gather_fast for a wavefront of an instance with x3 walls none of whose
+// lanes is within reach of them: x3 - c3 needs no wrap, so the in-row offset
+// is (x3 - c3) S + the x2 offset, and the constant -c3 S goes into the
+// wavefront-uniform row address. Five per-lane offsets (one per x2 shift)
+// serve all 41 loads, with no per-population address arithmetic.
+template <int ST, bool EQW = false, class R>
+__device__ __forceinline__ void gather_fast_walled3(const void *src, const InstDesc &d, int x1, int x2, int x3,
+                                                    const R &ref, typename Codec<ST>::G (&g)[Q])
+{
+    using T = typename Codec<ST>::T;
+    using C = typename Codec<ST>::C;
+    constexpr uint64_t S = sizeof(T);
+    const bool per1 = !(d.walls & 1);
+    const uint64_t PS = (uint64_t)d.Pp * S;
+    int rows[5];      // source row x1 - CVALS[s]
+    uint64_t rb[5];   // byte offset of plane 0 of that row
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        int r1 = x1 - CVALS[k];
+        if (per1) r1 = wrap_axis(r1, d.n1);
+        if (EQW && d.eqwall) r1 = r1 < 0 ? 0 : (r1 > d.n1 - 1 ? d.n1 - 1 : r1);
+        rows[k] = r1;
+        rb[k] = (uint64_t)r1 * (uint64_t)Q * PS;
+    }
+    uint32_t o[5];    // in-row byte offset of (x2 - CVALS[s], x3)
+#pragma unroll
+    for (int s = 0; s < 5; ++s) o[s] = (uint32_t)(wrap_axis(x2 - CVALS[s], d.n2) * d.n3p + x3) * (uint32_t)S;
+    static_for<0, Q>([&](auto q) {
+        constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
+        const char *rowp = (const char *)src + rb[cslot(c1)] + (uint64_t)q * PS - (int64_t)c3 * (int64_t)S;
+        const C r = Codec<ST>::REF ? (C)ref.get_r(c1, rows[cslot(c1)], q) : C(0);
+        g[q] = decode_wave<ST, R>(gload<T>(rowp, o[cslot(c2)]), r);
     });
 }
 
@@ -568,7 +621,10 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
             if constexpr (m == 1) {
                 const uint32_t o0 = rb[3] + base + L.o2[2] + x3S;            // sb = 0: the node itself
                 off = dist == 0 ? o0 : off;
-                if constexpr (REF) r = dist == 0 ? (C)ref.get_r(0, rows[3], qo) : r;
+                if constexpr (REF) {
+                    const C r0 = (C)ref.get_r(0, rows[3], qo);   // read unconditionally, then select
+                    r = dist == 0 ? r0 : r;
+                }
             } else {
                 const uint32_t oa = rb[3 - 2 * h1] + base + o2t[3 - 2 * h2] + (uint32_t)((int)x3S + 2 * h3 * (int)S);
                 const uint32_t ob = rb[3] + base + L.o2[2] + x3S;
@@ -582,7 +638,8 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
                 }
             }
         }
-        g[q] = Codec<ST>::decode(gload<T>(src, (uint64_t)off), r);
+        if constexpr (c3 != 0) g[q] = decode_lane<ST>(gload<T>(src, (uint64_t)off), r);   // r chosen per lane
+        else g[q] = decode_wave<ST, R>(gload<T>(src, (uint64_t)off), r);
     });
 }
 

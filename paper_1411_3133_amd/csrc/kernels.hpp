@@ -13,6 +13,7 @@ struct StepArgs {
     const int *ntiles;       // device: number of queued tiles
     double *partials;        // [tiles][3] check sums
     int parity;              // read f[parity], write f[parity ^ 1]
+    int xcd_group = 0;       // 1: each XCD takes a contiguous eighth of the tile queue
 };
 
 hipError_t launch_step(const StepArgs &a, int pat, int st, bool check, bool eqw, int grid, int block, hipStream_t s);

@@ -37,8 +37,17 @@ hipError_t launch_step_plain(const StepArgs &a, int pat, int st, bool check, int
     }
 }
 
-hipError_t launch_step(const StepArgs &a, int pat, int st, bool check, bool eqw, int grid, int block, hipStream_t s)
+hipError_t launch_step(const StepArgs &a0, int pat, int st, bool check, bool eqw, int grid, int block, hipStream_t s)
 {
+    // Tile order. Grouped by XCD, the x3 pulls that straddle a cache line at
+    // a tile boundary find it in their own L2: the 16-bit formats then fetch
+    // 1.02x their algorithmic bytes instead of 1.39x at the same speed (they
+    // are bound by arithmetic). The wide formats are bound by HBM, and there
+    // interleaved tiles are faster (68.7 % against 66.4 % of 8 TB/s on the
+    // cylinder sweep in FP32, 70.5 % against 65.1 % on the 96x192x192
+    // instance): all XCDs then stream through neighbouring memory at once.
+    StepArgs a = a0;
+    a.xcd_group = (st == ST_F16 || st == ST_BF16) ? 1 : 0;
     return eqw ? launch_step_eq(a, pat, st, check, grid, block, s) : launch_step_plain(a, pat, st, check, grid, block, s);
 }
 

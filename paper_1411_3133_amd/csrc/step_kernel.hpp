@@ -9,9 +9,9 @@
 // branch-free variant that resolves the single x3 reflection per lane, rows
 // next to an x1 wall one whose reflections are uniform per wavefront;
 // wavefronts at a corner of both take the general fold.  The launch is persistent: workgroups
-// stride over the flat tile queue of all active instances, and the number
-// of queued tiles is read from device memory so that a captured graph stays
-// valid when instances retire.
+// stride over the flat tile queue of all active instances (grouped by XCD
+// for the 16-bit formats), and the number of queued tiles is read from device memory so that a
+// captured graph stays valid when instances retire.
 //
 // With equilibrium walls (Sec. III) the first and last x1 rows are wall
 // nodes: pulls from beyond them read the wall row, and a wall row is set to
@@ -38,25 +38,36 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
     using C = typename Codec<ST>::C;
     __shared__ double red[8][3];
 
-    const int ntiles = *a.ntiles;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const Tile tl = a.tiles[t];
-        const InstDesc &d = a.insts[tl.inst];
+    const int ntiles = load_uniform(a.ntiles);
+    // Workgroups go to the 8 XCDs round-robin (v mod 8), and each XCD has
+    // its own L2. Neighbouring tiles of a row share the cache lines that
+    // their x3 pulls straddle; with xcd_group each XCD takes one contiguous
+    // eighth of the queue instead of every eighth tile, so that a straddled
+    // line is fetched once, not by two XCDs. (A bijection of [0, ntiles);
+    // with a persistent grid that is a multiple of 8 it holds on every pass.)
+    const int per = ntiles >> 3, rem = ntiles & 7;
+    for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+        const int xcd = v & 7;
+        const int t = a.xcd_group ? xcd * per + min(xcd, rem) + (v >> 3) : v;
+        const Tile tl = load_uniform(a.tiles + t);
+        const InstDesc d = load_uniform(a.insts + tl.inst);
         const int x1 = tl.x1;
         // storage column col = x2 * n3p + x3s. Lanes on the x3 padding
         // (x3s >= n3) repeat the row's last node and store the copy into the
         // padding, so that every 64-byte segment of a row is written whole
         // (a partly written segment costs the memory a read-modify-write:
         // 19 % of the step time at n3 = 113); nothing ever reads the copies.
-        const int col = tl.chunk * (int)blockDim.x + (int)threadIdx.x;
-        const int colc = col < d.Pp ? col : 0;
-        const int x2 = (int)(((uint64_t)colc * d.n3_magic) >> 40);
-        const int x3s = colc - x2 * d.n3p;
+        const int lane = tl.chunk * (int)blockDim.x + (int)threadIdx.x;
+        const bool valid = lane < d.Pp;              // the lane owns a storage column
+        const int col = valid ? lane : 0;
+        const int x2 = (int)(((uint64_t)col * d.n3_magic) >> 40);
+        const int x3s = col - x2 * d.n3p;
         const int x3 = x3s < d.n3 ? x3s : d.n3 - 1;
-        const bool valid = col < d.Pp;               // the lane owns a storage column
         const bool real = valid && x3s < d.n3;       // ... that holds a node
-        const void *src = d.f[a.parity];
-        void *dst = d.f[a.parity ^ 1];
+        // selects, not an indexed read: a run-time index into the local copy
+        // of the descriptor would move the whole copy to scratch memory
+        const void *src = a.parity ? d.f[1] : d.f[0];
+        void *dst = a.parity ? d.f[0] : d.f[1];
         constexpr uint32_t S = sizeof(T);
         const RefScalar R{d.ref};
         uint32_t ctr = 0;                      // step counter of the stochastic rounding
@@ -78,9 +89,11 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
         double dsq = 0.0, usq = 0.0, badf = 0.0;
         if (valid) {
             typename Codec<ST>::G g[Q];
-            if (!wall1_row && !any3) {
+            if (!wall1_row && !any3 && (d.walls & 4)) {
+                gather_fast_walled3<ST, EQW>(src, d, x1, x2, x3, R, g);
+            } else if (!wall1_row && !any3) {
                 LaneOffsets L;
-                L.init(x2, x3, d.n2, d.n3, d.n3p, !(d.walls & 4), S);
+                L.init(x2, x3, d.n2, d.n3, d.n3p, true, S);
                 gather_fast<ST, EQW>(src, d, x1, L, R, g);
             } else if (!wall1_row && d.n3 >= 5) {
                 LaneOffsets L;

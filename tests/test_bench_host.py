@@ -27,7 +27,7 @@ def test_digest_ignores_comments_and_sees_code():
 
 @pytest.mark.parametrize("tag", ["uneven_ellipsoid_batch_f32", "cylinder_sweep_64x4x256_f32",
                                  "cylinder_sweep_64x4x256_f64", "cylinder_sweep_64x4x256_f16",
-                                 "ellipsoid_96x192x192_f32"])
+                                 "ellipsoid_96x192x192_f32", "ellipsoid_96x384x192_f16"])
 def test_committed_counter_summaries_match_the_kernel(tag):
     """A code change to the step kernel voids the committed summaries; they
     are taken again before such a change is committed."""
