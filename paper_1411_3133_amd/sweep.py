@@ -23,7 +23,7 @@ from . import warmstart as W
 from .mlbm import Net
 
 
-def _run(cases, inits_plain, tol, max_steps, net=None, fallback_after=None, log=None):
+def _run(cases, inits_plain, tol, max_steps, net=None, fallback_after=None, log=None, stall_chunks=3, chunk=5000):
     """Fields, steps, status, observables (<omega>, <v_theta>, measured De),
     seconds and the indices of runs that fell back to the plain start, of a
     batch of cases."""
@@ -34,7 +34,7 @@ def _run(cases, inits_plain, tol, max_steps, net=None, fallback_after=None, log=
         b.close()
         return fields, steps, status, obs, secs, []
     fields, steps, status, secs, _, redo, _, obs = W.warm_start_run(net, cases, inits_plain, tol, max_steps,
-                                                                    fallback_after, log)
+                                                                    fallback_after, log, stall_chunks, chunk)
     return fields, steps, status, obs, secs, list(redo)
 
 
@@ -83,11 +83,14 @@ def knee(De: Sequence[float], omega: Sequence[float]):
 
 def critical_dean(pairs: Sequence[Tuple], De_grid, ks: Sequence[int] = (2, 4, 6), rel_width: float = 0.01,
                   tol: float = 1e-6, max_steps: int = 200000, seed: int = 7, net: Optional[Net] = None,
-                  fallback_after: int = 60000, log=None) -> Dict:
+                  fallback_after: Optional[int] = 60000, log=None, stall_chunks: int = 3,
+                  chunk: int = 5000) -> Dict:
     """Bracket the onset De of k cells for every pair ((name, make) or
     (name, make, De_top)); De_grid is one sequence of De for every pair, or a
     callable De_top -> sequence. With `net` every run starts from its
-    prediction (plain start as fallback where a warm run stalls). Returns
+    prediction (plain start as fallback where a warm run stalls: no 20 %
+    fall of its residual over stall_chunks chunks of `chunk` steps, or not
+    converged after fallback_after steps; None: the whole budget). Returns
     brackets of nominal and measured De per (pair, k), the onset read off
     each pair's <omega>(measured De) curve of converged runs (`knee`), the
     cell counts and <omega> seen, wall time, instance-steps and fallbacks
@@ -101,7 +104,8 @@ def critical_dean(pairs: Sequence[Tuple], De_grid, ks: Sequence[int] = (2, 4, 6)
     def run_round(items):
         cases = [make(De) for (_, make, De) in items]
         plain = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
-        fields, steps, status, obs, secs, redo = _run(cases, plain, tol, max_steps, net, fallback_after, log)
+        fields, steps, status, obs, secs, redo = _run(cases, plain, tol, max_steps, net, fallback_after, log,
+                                                      stall_chunks, chunk)
         for j, ((name, _, De), c, (_, u), st, ob) in enumerate(zip(items, cases, fields, status, obs)):
             seen[(name, De)] = (W.cell_count(c, u), float(ob[2]), int(st), float(ob[0]),
                                 net is not None and j not in redo)
