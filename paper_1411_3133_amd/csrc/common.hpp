@@ -167,7 +167,8 @@ __device__ __forceinline__ uint16_t float_to_bf16_bits_sr(float x, uint32_t seed
     return (uint16_t)v;
 }
 
-// 32-bit integer hash (xorshift-multiply, two rounds).
+// 32-bit integer hash (xorshift-multiply, two rounds): the published
+// "lowbias32" constants of C. Wellons' hash-prospector search.
 __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x)
 {
     x ^= x >> 16;
