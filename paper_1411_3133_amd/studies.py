@@ -11,9 +11,21 @@ onsets by cell count, and the onset read off the <omega> curve (`sweep.knee`)
 (r u^theta averaged over the cross section, the library's) and r_i <u^theta>
 (the angular velocity times the inner radius).
 
+`paper_ellipsoid_sweep` is Sec. IV's pair of studies on the double-curved
+channel at the paper's cross-section, L_r x L_phi = 64 x 128 spacings,
+tau = 1, with the aspect ratio eta = 0.9 of r_i = 1 (d = 0.111 r_i):
+"b" varies the streamwise curvature R_theta = r_i b^2 at R_phi = r_i = 1
+(Sec. IV A), "ri" varies R_phi = r_i at R_theta = 1 (Sec. IV B). In the
+units of `cases.ellipsoid_case` (d = 1) that is R1/d = 9 R_theta and
+R2/d = 9 R_phi. The slab is streamwise periodic with the metric frozen at
+theta = 0 (four theta slabs), so the open theta ends of Sec. IV are not
+modelled. It reports the knee of <omega> against the measured De and the
+2-, 4- and 6-cell onsets by cell count per curvature.
+
 Run as `python -m paper_1411_3133_amd.studies eta --walls bounce|equilibrium`
-(one MI355X); it prints one JSON document. Orchestration only: every step
-runs in libmlbm's kernels.
+or `python -m paper_1411_3133_amd.studies ellipsoid --sweep b|ri` (one
+MI355X); each prints one JSON document. Orchestration only: every step runs
+in libmlbm's kernels.
 """
 from __future__ import annotations
 
@@ -77,19 +89,80 @@ def paper_cylinder_eta_sweep(etas=(0.8, 0.85, 0.9, 0.95), walls="bounce", De_gri
     return out
 
 
+def _onsets(rows, key, reading="De_measured", ks=(2, 4, 6)):
+    """Knee of <omega> over the converged runs and cell-count brackets
+    (last run below, first at or above k cells) of one curve."""
+    rs = sorted(rows, key=lambda r: r["De_nominal"])
+    ok = [r for r in rs if r["status"] == 0]
+    res = {"knee": sweep.knee([r[reading] for r in ok], [r["omega"] for r in ok]) if len(ok) >= 4 else None}
+    for k in ks:
+        first = next((j for j, r in enumerate(rs) if r["cells"] >= k), None)
+        res[f"k{k}"] = None if first is None else [rs[first - 1][reading] if first > 0 else None,
+                                                   rs[first][reading]]
+    return res
+
+
+def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=None, tol=1e-8,
+                          max_steps=600_000, precision="f64", seed=1411, log=None):
+    """Sec. IV A ("b": values are R_theta = b^2 at r_i = 1) or Sec. IV B ("ri":
+    values are R_phi = r_i at R_theta = 1), all curvatures and De of one
+    study in one batch run to a steady state."""
+    if values is None:
+        values = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2, 1.4) if which == "b" else \
+                 (0.8, 0.9, 1.0, 1.1, 1.2, 1.4, 1.55, 1.8)
+    if De_grid is None:
+        De_grid = [float(d) for d in range(14, 49, 2)]
+    eq = walls == "equilibrium"
+    cases, meta = [], []
+    for v in values:
+        R_th, R_ph = (v, 1.0) if which == "b" else (1.0, v)
+        for De in De_grid:
+            # 64 radial spacings: 64 fluid rows between halfway walls, or 65
+            # rows of which the first and last are the wall nodes
+            cases.append(K.ellipsoid_case(9.0 * R_th, 9.0 * R_ph, 65 if eq else 64, 4, 128, 1.0, De=De,
+                                          precision=precision, eq_walls=eq,
+                                          label=f"ell-{which}{v:g}-{walls}-De{De:g}"))
+            meta.append((v, R_th, R_ph))
+    inits = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
+    t0 = time.perf_counter()
+    b, steps, status, secs = W.run_to_steady(cases, inits, tol, max_steps, chunk=50000, log=log)
+    rows = []
+    for i, c in enumerate(cases):
+        om, vm, De_m = b[i].vortex_intensity()
+        _, u = b[i].moments()
+        v, R_th, R_ph = meta[i]
+        rows.append({"value": v, "R_theta": R_th, "R_phi": R_ph, "De_nominal": c.target_De, "De_measured": De_m,
+                     "omega": om, "cells": W.cell_count(c, u), "steps": int(steps[i]), "status": int(status[i])})
+    b.close()
+    out = {"study": which, "walls": walls, "precision": precision, "tol": tol, "max_steps": max_steps, "tau": 1.0,
+           "grid": "64 x 4 x 128 spacings (r, theta slab, phi)", "seconds": round(time.perf_counter() - t0, 1),
+           "runs": rows, "onsets": {}}
+    for v in values:
+        out["onsets"][f"{v:g}"] = _onsets([r for r in rows if r["value"] == v], v)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["eta"])
-    ap.add_argument("--walls", choices=["bounce", "equilibrium"], default="bounce")
+    ap.add_argument("study", choices=["eta", "ellipsoid"])
+    ap.add_argument("--walls", choices=["bounce", "equilibrium"], default=None,
+                    help="default: bounce-back for eta, equilibrium (the paper's) for ellipsoid")
     ap.add_argument("--etas", default="0.8,0.85,0.9,0.95")
-    ap.add_argument("--max-steps", type=int, default=1_000_000)
-    ap.add_argument("--tol", type=float, default=1e-9)
+    ap.add_argument("--sweep", choices=["b", "ri"], default="b")
+    ap.add_argument("--values", default=None, help="comma-separated R_theta (b) or R_phi (ri) values")
+    ap.add_argument("--max-steps", type=int, default=None)
+    ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--precision", default="f64")
     args = ap.parse_args()
-    etas = tuple(float(x) for x in args.etas.split(","))
-    res = paper_cylinder_eta_sweep(etas, args.walls, tol=args.tol, max_steps=args.max_steps,
-                                   precision=args.precision,
-                                   log=lambda m: print(m, file=sys.stderr, flush=True))
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.study == "eta":
+        etas = tuple(float(x) for x in args.etas.split(","))
+        res = paper_cylinder_eta_sweep(etas, args.walls or "bounce", tol=args.tol or 1e-9,
+                                       max_steps=args.max_steps or 1_000_000, precision=args.precision, log=log)
+    else:
+        values = None if args.values is None else tuple(float(x) for x in args.values.split(","))
+        res = paper_ellipsoid_sweep(args.sweep, values, args.walls or "equilibrium", tol=args.tol or 1e-8,
+                                    max_steps=args.max_steps or 600_000, precision=args.precision, log=log)
     print(json.dumps(res), flush=True)
 
 

@@ -1,0 +1,92 @@
+"""Host logic of the paper-scale studies (no GPU): the batched run to a
+steady state is replaced by fields whose cell count and vorticity switch at
+known Dean numbers, so the study must build the paper's cases (Sec. III:
+cylinder 128 x 1 x 256 spacings, tau = 0.9; Sec. IV: 64 x 128 spacings,
+tau = 1, R1/d = 9 R_theta, R2/d = 9 R_phi) and read the onsets back."""
+import numpy as np
+import pytest
+
+from paper_1411_3133_amd import cases as K
+from paper_1411_3133_amd import studies
+from paper_1411_3133_amd import warmstart as W
+
+ONSET = 31.0        # nominal De of the 2-cell onset in the fake runs
+
+
+class _Inst:
+    def __init__(self, case):
+        self.case = case
+
+    def vortex_intensity(self):
+        De = 0.95 * self.case.target_De
+        om = 1e-3 + 0.02 * max(0.0, De - 0.95 * ONSET)       # a knee at measured 0.95 ONSET
+        return om, 1.0, De
+
+    def moments(self):
+        c = self.case
+        u = np.zeros((3, c.n1, c.n2, c.n3))
+        u[1] = 1.0
+        if c.target_De >= ONSET:
+            x = (np.arange(c.n3) + 0.5) / c.n3
+            u[0, c.n1 // 2] = 0.1 * K.nominal_velocity(c, c.target_De) * np.sin(2 * np.pi * x + 0.3)[None, :]
+        return np.ones((c.n1, c.n2, c.n3)), u
+
+
+class _Batch:
+    def __init__(self, cases):
+        self.cases = cases
+
+    def __getitem__(self, i):
+        return _Inst(self.cases[i])
+
+    def close(self):
+        pass
+
+
+@pytest.fixture
+def fake_steady(monkeypatch):
+    seen = []
+
+    def run_to_steady(cases, inits, tol, max_steps, **kw):
+        seen.append(list(cases))
+        n = len(cases)
+        return _Batch(cases), np.full(n, 1000), np.zeros(n, np.int32), 0.01
+
+    monkeypatch.setattr(W, "run_to_steady", run_to_steady)
+    return seen
+
+
+@pytest.mark.parametrize("which,walls", [("b", "equilibrium"), ("ri", "bounce")])
+def test_ellipsoid_study_builds_the_paper_cases_and_reads_onsets(fake_steady, which, walls):
+    values = (0.8, 1.0, 1.4)
+    grid = [float(d) for d in range(20, 45, 2)]
+    r = studies.paper_ellipsoid_sweep(which, values, walls, De_grid=grid)
+    (cases,) = fake_steady
+    assert len(cases) == len(values) * len(grid)
+    for c, row in zip(cases, r["runs"]):
+        assert c.kind == "ellipsoid" and c.tau == 1.0 and c.n3 == 128 and c.n2 == 4
+        assert c.n1 == (65 if walls == "equilibrium" else 64) and c.eq_walls == (walls == "equilibrium")
+        v = row["value"]
+        R_th, R_ph = (v, 1.0) if which == "b" else (1.0, v)
+        assert c.r_inner == pytest.approx(9.0 * R_ph)                 # R2/d = R_phi / d, d = r_i / 9
+        assert c.r_inner * c.b ** 2 == pytest.approx(9.0 * R_th)      # R1/d = r_i b^2 / d
+        assert (row["R_theta"], row["R_phi"]) == (R_th, R_ph)
+    for v in values:
+        o = r["onsets"][f"{v:g}"]
+        lo, hi = o["k2"]
+        assert lo < 0.95 * ONSET <= hi and hi - lo == pytest.approx(0.95 * 2.0)
+        assert o["k4"] is None and o["k6"] is None
+        assert o["knee"] == pytest.approx(0.95 * ONSET, abs=0.6)
+
+
+def test_eta_study_builds_the_paper_channel(fake_steady):
+    r = studies.paper_cylinder_eta_sweep((0.8, 0.9), "equilibrium", De_grid=[float(d) for d in range(24, 41, 2)])
+    (cases,) = fake_steady
+    for c in cases:
+        assert c.kind == "cylinder" and c.tau == 0.9 and (c.n1, c.n2, c.n3) == (129, 1, 256)
+        assert c.eq_walls and not (c.walls & K.WALL_AXIS3)
+        eta = c.r_inner / (c.r_inner + c.width)
+        assert eta == pytest.approx(0.8) or eta == pytest.approx(0.9)
+    for eta in ("0.8", "0.9"):
+        lo, hi = r["onsets"][eta]["De_measured"]["k2"]
+        assert lo < 0.95 * ONSET <= hi
