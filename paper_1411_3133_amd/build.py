@@ -58,7 +58,8 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
             print(text, flush=True)
     if failed:
         raise RuntimeError("hipcc failed for " + ", ".join(failed))
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs + \
+          ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -19,8 +19,9 @@ u^i = dx^i/dt, laid out [3][n1][n2][n3].
 from __future__ import annotations
 
 import dataclasses
+import json
 import math
-from typing import List, Optional
+from typing import List, Optional, Sequence
 
 import numpy as np
 
@@ -434,3 +435,83 @@ def net_init_params(hidden: int, depth: int, seed: int = 2024) -> np.ndarray:
         out.append(a * uniform_pm1(seed, ni * no, stream=100 + l))
         out.append(np.zeros(no))
     return np.concatenate(out)
+
+# ---------------------------------------------------------------------------
+# JSON case files: a list of cases plus the start of each run (the perturbed
+# laminar start with its seed and amplitude), written and read back without
+# loss; `python -m paper_1411_3133_amd.cases <workload> > file.json` writes
+# one of the named workloads below.
+# ---------------------------------------------------------------------------
+
+CASE_FILE_FORMAT = "mlbm-cases/1"
+
+
+def case_to_dict(c: Case) -> dict:
+    return dataclasses.asdict(c)
+
+
+def case_from_dict(d: dict) -> Case:
+    names = {f.name for f in dataclasses.fields(Case)}
+    unknown = set(d) - names
+    if unknown:
+        raise ValueError(f"unknown case fields: {sorted(unknown)}")
+    return Case(**d)
+
+
+def cases_to_json(cases: Sequence[Case], seeds: Sequence[int], amp: float = 1e-4, meta: Optional[dict] = None) -> str:
+    if len(seeds) != len(cases):
+        raise ValueError("one seed per case")
+    return json.dumps({"format": CASE_FILE_FORMAT, "meta": meta or {},
+                       "runs": [{"case": case_to_dict(c), "start": {"kind": "perturbed", "seed": int(s), "amp": amp}}
+                                for c, s in zip(cases, seeds)]}, indent=1)
+
+
+def cases_from_json(text: str):
+    """(cases, starts, meta) of a case file; starts[i] = (seed, amp)."""
+    doc = json.loads(text)
+    if doc.get("format") != CASE_FILE_FORMAT:
+        raise ValueError(f"not a {CASE_FILE_FORMAT} file")
+    cases, starts = [], []
+    for r in doc["runs"]:
+        cases.append(case_from_dict(r["case"]))
+        st = r.get("start", {"kind": "perturbed", "seed": 0, "amp": 0.0})
+        if st.get("kind") != "perturbed":
+            raise ValueError(f"unknown start kind {st.get('kind')!r}")
+        starts.append((int(st["seed"]), float(st["amp"])))
+    return cases, starts, doc.get("meta", {})
+
+
+def named_workload(name: str, precision: Optional[str] = None):
+    """(cases, seeds, meta) of the workloads the benchmark and tests use."""
+    if name == "laminar_cylinder":
+        cs = [laminar_cylinder(precision or "f64")]
+        return cs, [0], {"workload": "laminar curved channel (cylinder 16 x 4 x 32, eta 0.9, De 20)"}
+    if name == "cylinder_sweep":
+        cs = cylinder_sweep(precision=precision or "f32")
+        return cs, [1411 + i for i in range(len(cs))], {"workload": "curved-channel sweep near transition"}
+    if name == "uneven_batch":
+        cs = uneven_ellipsoid_batch(precision=precision or "f32")
+        return cs, [3133 + i for i in range(len(cs))], {"workload": "batched uneven double-curved sweep"}
+    if name == "ellipsoid_96x192":
+        cs = ellipsoid_96x192_cases(precision=precision or "f32")
+        return cs, [96 + i for i in range(len(cs))], {"workload": "96 x 192 double-curved cross sections"}
+    if name == "warmstart_unseen":
+        cs = warmstart_cases(64, seed=9001)
+        return cs, [500 + i for i in range(len(cs))], {"workload": "warm-start study, unseen cases"}
+    raise ValueError(f"unknown workload {name!r}")
+
+
+def _main():
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser(description="write a named workload as a JSON case file to stdout")
+    ap.add_argument("workload", choices=["laminar_cylinder", "cylinder_sweep", "uneven_batch", "ellipsoid_96x192",
+                                         "warmstart_unseen"])
+    ap.add_argument("--precision", default=None)
+    args = ap.parse_args()
+    cs, seeds, meta = named_workload(args.workload, args.precision)
+    sys.stdout.write(cases_to_json(cs, seeds, meta=dict(meta, name=args.workload)) + "\n")
+
+
+if __name__ == "__main__":
+    _main()

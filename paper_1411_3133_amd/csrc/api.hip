@@ -20,6 +20,8 @@
 #include <vector>
 
 #include "../../include/mlbm.h"
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include "common.hpp"
 #include "core.hpp"
 #include "kernels.hpp"
@@ -507,7 +509,11 @@ mlbm_status advance(Batch *B, int64_t n)
                 mlbm_status s = capture_window(B);
                 if (s != MLBM_OK) return s;
             }
-            HIP_TRY(hipGraphLaunch(B->graph, B->stream));
+            // one host range per K-step window (rocprofv3 --marker-trace)
+            roctxRangePushA("mlbm K-step window");
+            const hipError_t e = hipGraphLaunch(B->graph, B->stream);
+            roctxRangePop();
+            HIP_TRY(e);
             B->t += B->K;
             for (auto &I : B->inst)
                 if (I.active) I.t += B->K;

@@ -28,7 +28,8 @@ def case_params(case: K.Case):
 
 
 def run_to_steady(cases: Sequence[K.Case], inits, tol: float, max_steps: int, chunk: int = 20000,
-                  log=None, stream=None, stall_chunks: Optional[int] = None, stall_factor: float = 0.8):
+                  log=None, stream=None, stall_chunks: Optional[int] = None, stall_factor: float = 0.8,
+                  on_chunk=None):
     """Batched run to residual <= tol; returns (batch, steps, status, seconds).
     status: 0 converged, 1 step cap, 2 unstable, 3 stalled. Converged and
     unstable instances leave the batch at once and are not stepped again.
@@ -36,7 +37,9 @@ def run_to_steady(cases: Sequence[K.Case], inits, tol: float, max_steps: int, ch
     stall_factor times its best value for that many chunks (and is still
     above 10 tol) is retired as stalled. The time includes creating the
     batch (geometry and initial populations); on return every instance is
-    back in the batch, in the state it stopped in."""
+    back in the batch, in the state it stopped in. on_chunk(batch, total,
+    steps, residuals, status, chunk_steps, chunk_seconds) is called after
+    every chunk (the run's metrics log)."""
     t0 = time.perf_counter()
     b = Batch(cases, inits, stream=stream)
     b.keep_retired(True)
@@ -48,7 +51,9 @@ def run_to_steady(cases: Sequence[K.Case], inits, tol: float, max_steps: int, ch
     since = np.zeros(n, np.int64)
     total = 0
     while total < max_steps and not done.all():
+        tc = time.perf_counter()
         st, res, sta = b.run_until(tol, min(chunk, max_steps - total))
+        tc = time.perf_counter() - tc
         for i in range(n):
             if not done[i]:
                 steps[i] = total + st[i]
@@ -69,6 +74,8 @@ def run_to_steady(cases: Sequence[K.Case], inits, tol: float, max_steps: int, ch
                     b.retire(int(i))
                     done[i] = True
                     status[i] = 3
+        if on_chunk:
+            on_chunk(b, total, steps.copy(), res.copy(), status.copy(), st.copy(), tc)
         if log:
             log(f"  t={total} converged={int((status == 0).sum())} unstable={int((status == 2).sum())} "
                 f"stalled={int((status == 3).sum())} elapsed={time.perf_counter() - t0:.1f}s")

@@ -71,3 +71,23 @@ def test_dean_cell_slab_steady_state_fp64_against_oracle():
     assert err < (1e-10 if int(steps[0]) == steps_o else 2e-6)
     assert cells_o == cells == 2
     assert abs(om / obs_o[0] - 1.0) < 1e-6 and abs(De / obs_o[2] - 1.0) < 1e-6
+
+
+def test_case_file_run_logs_metrics(tmp_path):
+    """The JSON-case runner on the laminar cylinder in FP32: the run
+    converges, every chunk line carries the observables and rate, and the
+    last chunk's De is the converged one."""
+    import io
+    import json
+    from paper_1411_3133_amd import run as R
+    cs, seeds, meta = K.named_workload("laminar_cylinder", "f32")
+    out = io.StringIO()
+    summary = R.run_case_file(K.cases_to_json(cs, seeds, meta=dict(meta, name="laminar_cylinder")),
+                              1e-6, 20000, 1000, out)
+    lines = [json.loads(x) for x in out.getvalue().splitlines()]
+    assert summary["converged"] == 1 and lines[-1] == summary
+    chunks = lines[:-1]
+    assert len(chunks) >= 2
+    assert all(c["MLUPS"] > 0 and 0 < c["hbm_frac"] < 1 and c["precision"] == "f32" for c in chunks)
+    assert chunks[-1]["status"] == 0 and chunks[-1]["residual"] <= 1e-6
+    assert abs(chunks[-1]["De"] / 19.66 - 1.0) < 1e-3
