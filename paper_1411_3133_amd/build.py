@@ -67,5 +67,47 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     return LIB
 
 
+# The runtime sanitizer driver (tests/native/api_sanitize.cpp): the host
+# code of the runtime sources with AddressSanitizer and UndefinedBehavior-
+# Sanitizer (host compilation only; the GPU code is built as usual), linked
+# with the ordinary kernel objects of build().
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+SANITIZED = ["api.hip", "mlp.hip"]
+DRIVER_SRC = os.path.join(HERE, "..", "tests", "native", "api_sanitize.cpp")
+DRIVER = os.path.join(HERE, "api_sanitize")   # next to the library: it ships to the GPU with it
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    objs = [os.path.join(BUILD, s.replace(".hip", ".o")) for s in SOURCES if s not in SANITIZED]
+    missing = [o for o in objs if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError("build() first: missing " + ", ".join(missing))
+    cmds = []
+    for src in SANITIZED:
+        obj = os.path.join(BUILD, "asan_" + src.replace(".hip", ".o"))
+        objs.append(obj)
+        cmds.append([HIPCC] + FLAGS + SANITIZE + ["-c", os.path.join(CSRC, src), "-o", obj])
+    drv = os.path.join(BUILD, "asan_driver.o")
+    objs.append(drv)
+    cmds.append([HIPCC, "-x", "c++", "-std=c++17", "-O1"] + SANITIZE + ["-c", DRIVER_SRC, "-o", drv])
+    procs = [(c, subprocess.Popen(c, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)) for c in cmds]
+    for c, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            print(out.decode(errors="replace"), file=sys.stderr, flush=True)
+            raise RuntimeError("hipcc failed: " + " ".join(c))
+        if verbose:
+            print(" ".join(c), flush=True)
+    cmd = [HIPCC, "--offload-arch=gfx950", "-o", DRIVER] + objs + SANITIZE[:4] + \
+          ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return DRIVER
+
+
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)
+    if "--sanitized" in sys.argv:
+        build_sanitized(verbose="-v" in sys.argv)
