@@ -72,7 +72,7 @@ typedef enum {
  * grouped into calls, batches or graphs. mlbm_set_populations and the
  * initial state round to nearest. */
 
-enum { MLBM_WALL_AXIS1 = 1, MLBM_WALL_AXIS3 = 4, MLBM_WALL_EQUILIBRIUM = 8 };
+enum { MLBM_WALL_AXIS1 = 1, MLBM_WALL_AXIS3 = 4, MLBM_WALL_EQUILIBRIUM = 8, MLBM_OPEN_AXIS2 = 16 };
 enum { MLBM_FORCING_IMPROVED = 0, MLBM_FORCING_OLD = 1 };
 
 /* Problem description, following the paper's statement of the problem
@@ -81,8 +81,9 @@ enum { MLBM_FORCING_IMPROVED = 0, MLBM_FORCING_OLD = 1 };
  *  kind          mlbm_kind.
  *  n1, n2, n3    nodes along r, theta, z/phi; each >= 1, an axis with walls
  *                needs >= 4 nodes.
- *  walls         bit mask of MLBM_WALL_AXIS1 / MLBM_WALL_AXIS3; axes without
- *                walls (and axis 2 always) are periodic.  Walls are halfway
+ *  walls         bit mask of MLBM_WALL_AXIS1 / MLBM_WALL_AXIS3 /
+ *                MLBM_WALL_EQUILIBRIUM / MLBM_OPEN_AXIS2; axes without walls
+ *                (and axis 2 unless open) are periodic.  Walls are halfway
  *                bounce-back walls, half a spacing outside the first and
  *                last node (Dt = Dr = d / n1).  With MLBM_WALL_EQUILIBRIUM
  *                (needs MLBM_WALL_AXIS1 and a periodic axis 3) the axis-1
@@ -91,7 +92,12 @@ enum { MLBM_FORCING_IMPROVED = 0, MLBM_FORCING_OLD = 1 };
  *                (Dt = Dr = d / (n1 - 1)), set every step to f_eq(rho',
  *                u = 0) with rho' the density streamed into them; they do
  *                not collide, a pull from beyond a wall node reads the wall
- *                node, and their velocity is reported as 0.
+ *                node, and their velocity is reported as 0.  With
+ *                MLBM_OPEN_AXIS2 (n2 >= 4) axis 2 is open at both ends, the
+ *                inlet and outlet of Sec. IV: a pull from beyond an end slab
+ *                reads that end slab (the populations entering the domain
+ *                take the values they have at the end node); without it
+ *                axis 2 is periodic.
  *  forcing_mode  MLBM_FORCING_IMPROVED (a2 = a2_eq - sigma) or MLBM_FORCING_OLD.
  *  precision     mlbm_precision.
  *  check_every   K, steps per stationarity window (even, >= 2); 0 means 100.

@@ -43,8 +43,14 @@
  *     theta = 0 and the printed (theta independent) Christoffel symbols.
  *   - the full ellipsoid (ORC_ELLIPSOID_FULL) evaluates the metric of Sec. IV
  *     at every node's (r, theta, phi), non-diagonal off theta = 0, on a
- *     theta sector centred on 0 that is periodic in theta; the theta spacing
- *     is that of Sec. IV B unless the case gives one.
+ *     theta sector centred on 0 that is periodic in theta, or open at both
+ *     ends (ORC_OPEN2, any kind); the theta spacing is that of Sec. IV B
+ *     unless the case gives one.
+ *   - open theta ends (the inlet and outlet of Sec. IV, whose scheme the
+ *     paper does not give): a pull from beyond an end slab reads that end
+ *     slab, so the populations entering the domain take the values the same
+ *     populations have at the end node (zero gradient along theta); the flow
+ *     is driven by the body force, as in Sec. IV.
  *
  * Pins (tests that hold this code to facts fixed outside it):
  *   - lattice: the printed Table I (tests/golden/table1_weights.txt), the
@@ -66,6 +72,10 @@
  *     step, a cylinder at rest drains mass at rho' c_s^2 / r^2 per step
  *     (hydrostatic balance under the velocity reading), the window residual
  *     of a single decaying mode equals exp(lambda K) - 1;
+ *   - open theta ends: on a theta-invariant state they reproduce the
+ *     periodic run exactly, and a disturbance at the outlet slab reaches no
+ *     node of the inlet side in one step (nodes whose sources avoid it stay
+ *     exactly at rest);
  *   - observables: vorticity and mean velocity of closed-form fields.
  * Every function here has at least one such pin.
  *
@@ -358,6 +368,7 @@ void orc_metric(int kind, double b, double x1, double x2, double x3,
 /* ------------------------------------------------------------------------ */
 
 #define ORC_WALL_EQ 8   /* axis-1 walls are equilibrium walls with wall nodes */
+#define ORC_OPEN2 16    /* axis 2 (theta) open at both ends (Sec. IV inlet and outlet) */
 
 typedef struct {
     int kind;           /* ORC_FLAT, ORC_CYLINDER, ORC_ELLIPSOID                 */
@@ -410,9 +421,19 @@ static int wrap(int v, int n)
     return v < 0 ? v + n : v;
 }
 
+/* Axis 2 (theta): periodic, or open (ORC_OPEN2, the inlet and outlet of
+ * Sec. IV): a source beyond an end slab is that end slab, so a population
+ * entering the domain there takes the value the same population has at the
+ * end node (zero gradient along theta of the incoming populations). */
+static int axis2_source(const orc_case *cs, int v)
+{
+    if (cs->walls & ORC_OPEN2) return v < 0 ? 0 : (v > cs->n2 - 1 ? cs->n2 - 1 : v);
+    return wrap(v, cs->n2);
+}
+
 /* Pull source of population q at node x.  Axes with walls reflect the
  * backward trajectory (full velocity reversal, walls half a spacing outside
- * the end nodes); other axes are periodic.  Distances are counted in ticks of
+ * the end nodes); axis 2 follows axis2_source; other axes are periodic.  Distances are counted in ticks of
  * 1/(2m) time step, m = max|c_a|, so that every wall is at an odd tick and
  * every node at an even one. */
 static void pull_source(const orc_case *cs, const int x[3], int q, int src[3], int *qsrc)
@@ -424,6 +445,7 @@ static void pull_source(const orc_case *cs, const int x[3], int q, int src[3], i
         for (int a = 0; a < 3; ++a) {
             int v = x[a] - LC[q][a];
             if (a == 0) src[a] = v < 0 ? 0 : (v > n[0] - 1 ? n[0] - 1 : v);
+            else if (a == 1) src[a] = axis2_source(cs, v);
             else src[a] = wrap(v, n[a]);
         }
         *qsrc = q;
@@ -452,7 +474,7 @@ static void pull_source(const orc_case *cs, const int x[3], int q, int src[3], i
     for (int a = 0; a < 3; ++a) {
         int ch = LC[q][a] / m;
         int v = x[a] - ch * (int)(lam / 2);
-        src[a] = walled[a] ? v : wrap(v, n[a]);
+        src[a] = walled[a] ? v : (a == 1 ? axis2_source(cs, v) : wrap(v, n[a]));
     }
     *qsrc = (nref & 1) ? LOPP[q] : q;
 }

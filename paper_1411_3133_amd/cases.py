@@ -37,6 +37,9 @@ WALL_AXIS3 = 4
 # first and last x1 rows are wall nodes at r_i and r_o, so n1 - 1 spacings
 # span the channel (x3 must then be periodic).
 WALL_EQ = 8
+# Axis 2 (theta) open at both ends, the inlet and outlet of Sec. IV: a pull
+# from beyond an end slab reads that end slab.
+WALL_OPEN2 = 16
 
 
 @dataclasses.dataclass

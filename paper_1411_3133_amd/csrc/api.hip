@@ -173,8 +173,9 @@ mlbm_status validate(const mlbm_desc &d)
         return fail(MLBM_E_ARG, "kind must be MLBM_FLAT, MLBM_CYLINDER, MLBM_ELLIPSOID or MLBM_ELLIPSOID_FULL");
     if (!(d.dtheta >= 0.0) || !std::isfinite(d.dtheta)) return fail(MLBM_E_ARG, "dtheta must be >= 0");
     if (d.n1 < 1 || d.n2 < 1 || d.n3 < 1) return fail(MLBM_E_ARG, "n1, n2, n3 must be >= 1");
-    if ((d.walls & ~(MLBM_WALL_AXIS1 | MLBM_WALL_AXIS3 | MLBM_WALL_EQUILIBRIUM)) != 0)
+    if ((d.walls & ~(MLBM_WALL_AXIS1 | MLBM_WALL_AXIS3 | MLBM_WALL_EQUILIBRIUM | MLBM_OPEN_AXIS2)) != 0)
         return fail(MLBM_E_ARG, "walls: unknown bits");
+    if ((d.walls & MLBM_OPEN_AXIS2) && d.n2 < 4) return fail(MLBM_E_ARG, "an open axis 2 needs >= 4 nodes (n2)");
     if ((d.walls & MLBM_WALL_EQUILIBRIUM) && (d.walls & (MLBM_WALL_AXIS1 | MLBM_WALL_AXIS3)) != MLBM_WALL_AXIS1)
         return fail(MLBM_E_ARG, "equilibrium walls need walls on axis 1 and a periodic axis 3");
     if ((d.walls & MLBM_WALL_AXIS1) && d.n1 < 4) return fail(MLBM_E_ARG, "an axis with walls needs >= 4 nodes (n1)");
@@ -643,6 +644,7 @@ mlbm_status create_batch(const mlbm_desc *ds, int n, void *stream, Batch **out)
         if (ds[i].precision != ds[0].precision) return fail(MLBM_E_ARG, "every instance of a batch needs the same precision");
         if ((ds[i].check_every ? ds[i].check_every : 100) != K) return fail(MLBM_E_ARG, "every instance needs the same check_every");
         pat = std::max(pat, pattern_for_kind(ds[i].kind));
+        if (ds[i].walls & MLBM_OPEN_AXIS2) pat = PAT_GEN;   // open theta ends: general-pattern kernels
         eqw |= eq_walls(ds[i]);
     }
     if (const char *e = getenv("MLBM_PATTERN")) {   // compile-time sparsity override (tests of the general kernel)

@@ -411,6 +411,14 @@ __host__ __device__ __forceinline__ int wrap_axis(int v, int n)
     return v;
 }
 
+// Axis 2 (theta) is periodic, or open at both ends (walls bit 16, the inlet
+// and outlet of Sec. IV): a pull from beyond an end slab reads that end slab
+// (zero gradient along theta of the populations entering the domain).
+__host__ __device__ __forceinline__ int axis2(int v, int n2, bool open2)
+{
+    return open2 ? (v < 0 ? 0 : (v > n2 - 1 ? n2 - 1 : v)) : wrap_axis(v, n2);
+}
+
 constexpr int cslot(int c) { return c == -3 ? 0 : c == -1 ? 1 : c == 0 ? 2 : c == 1 ? 3 : 4; }
 constexpr int CVALS[5] = {-3, -1, 0, 1, 3};
 
@@ -496,11 +504,11 @@ __device__ __forceinline__ typename Codec<ST>::C decode_lane(typename Codec<ST>:
 
 struct LaneOffsets {
     uint32_t o2[5], o3[5];
-    __device__ __forceinline__ void init(int x2, int x3, int n2, int n3, int n3p, bool per3, uint32_t S)
+    __device__ __forceinline__ void init(int x2, int x3, int n2, int n3, int n3p, bool per3, bool open2, uint32_t S)
     {
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
-            o2[s] = (uint32_t)(wrap_axis(x2 - CVALS[s], n2) * n3p) * S;
+            o2[s] = (uint32_t)(axis2(x2 - CVALS[s], n2, open2) * n3p) * S;
             o3[s] = (uint32_t)(per3 ? wrap_axis(x3 - CVALS[s], n3) : x3 - CVALS[s]) * S;
         }
     }
@@ -542,7 +550,7 @@ __device__ __forceinline__ void gather_fast(const void *src, const InstDesc &d, 
 // is (x3 - c3) S + the x2 offset, and the constant -c3 S goes into the
 // wavefront-uniform row address. Five per-lane offsets (one per x2 shift)
 // serve all 41 loads, with no per-population address arithmetic.
-template <int ST, bool EQW = false, class R>
+template <int ST, bool EQW = false, bool OPEN2 = true, class R>
 __device__ __forceinline__ void gather_fast_walled3(const void *src, const InstDesc &d, int x1, int x2, int x3,
                                                     const R &ref, typename Codec<ST>::G (&g)[Q])
 {
@@ -562,8 +570,9 @@ __device__ __forceinline__ void gather_fast_walled3(const void *src, const InstD
         rb[k] = (uint64_t)r1 * (uint64_t)Q * PS;
     }
     uint32_t o[5];    // in-row byte offset of (x2 - CVALS[s], x3)
+    const bool open2 = OPEN2 && (d.walls & 16);
 #pragma unroll
-    for (int s = 0; s < 5; ++s) o[s] = (uint32_t)(wrap_axis(x2 - CVALS[s], d.n2) * d.n3p + x3) * (uint32_t)S;
+    for (int s = 0; s < 5; ++s) o[s] = (uint32_t)(axis2(x2 - CVALS[s], d.n2, open2) * d.n3p + x3) * (uint32_t)S;
     static_for<0, Q>([&](auto q) {
         constexpr int c1 = CV[q][0], c2 = CV[q][1], c3 = CV[q][2];
         const char *rowp = (const char *)src + rb[cslot(c1)] + (uint64_t)q * PS - (int64_t)c3 * (int64_t)S;
@@ -582,7 +591,7 @@ __device__ __forceinline__ void gather_fast_walled3(const void *src, const InstD
 // the plain pull. Candidates are formed from per-wave row offsets and
 // per-lane in-row offsets and chosen per lane by selects, so the path has
 // no branches; byte offsets fit in 32 bits (buffers are below 4 GiB).
-template <int ST, class R>
+template <int ST, bool OPEN2 = true, class R>
 __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d, int x1, int x2, int x3,
                                               const LaneOffsets &L, const R &ref, typename Codec<ST>::G (&g)[Q])
 {
@@ -602,8 +611,9 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
     }
     const uint32_t n3S = (uint32_t)d.n3p * S;
     // in-row x2 offsets of x2 - t for t = -3..3
-    const uint32_t o2t[7] = {L.o2[0], (uint32_t)wrap_axis(x2 + 2, d.n2) * n3S, L.o2[1], L.o2[2], L.o2[3],
-                             (uint32_t)wrap_axis(x2 - 2, d.n2) * n3S, L.o2[4]};
+    const bool open2 = OPEN2 && (d.walls & 16);
+    const uint32_t o2t[7] = {L.o2[0], (uint32_t)axis2(x2 + 2, d.n2, open2) * n3S, L.o2[1], L.o2[2], L.o2[3],
+                             (uint32_t)axis2(x2 - 2, d.n2, open2) * n3S, L.o2[4]};
     const uint32_t x3S = (uint32_t)x3 * S;
     const int dlo = x3, dhi = d.n3 - 1 - x3;
     static_for<0, Q>([&](auto q) {
@@ -650,7 +660,7 @@ __device__ __forceinline__ void gather_x3wall(const void *src, const InstDesc &d
 // sb = back - m are scalars: the source row and plane are uniform and only
 // the in-row offset of x - (c/m) sb varies per lane. One x1 crossing at
 // most (a single walled axis of >= 4 nodes), as in fold_source below.
-template <int ST, class R>
+template <int ST, bool OPEN2 = true, class R>
 __device__ __forceinline__ void gather_x1wall(const void *src, const InstDesc &d, int x1, int x2, int x3,
                                               const LaneOffsets &L, const R &ref, typename Codec<ST>::G (&g)[Q])
 {
@@ -661,7 +671,9 @@ __device__ __forceinline__ void gather_x1wall(const void *src, const InstDesc &d
     const uint32_t PS = (uint32_t)d.Pp * S;
     const uint32_t n3S = (uint32_t)d.n3p * S;
     // in-row offsets of x - t along x2 and x3 for t = -2, 0, 2 (index 0, 1, 2)
-    const uint32_t o2s[3] = {(uint32_t)wrap_axis(x2 + 2, d.n2) * n3S, L.o2[2], (uint32_t)wrap_axis(x2 - 2, d.n2) * n3S};
+    const bool open2 = OPEN2 && (d.walls & 16);
+    const uint32_t o2s[3] = {(uint32_t)axis2(x2 + 2, d.n2, open2) * n3S, L.o2[2],
+                             (uint32_t)axis2(x2 - 2, d.n2, open2) * n3S};
     const uint32_t o3s[3] = {(uint32_t)(per3 ? wrap_axis(x3 + 2, d.n3) : x3 + 2) * S, L.o3[2],
                              (uint32_t)(per3 ? wrap_axis(x3 - 2, d.n3) : x3 - 2) * S};
     const int lo = 2 * x1 + 1, hi = 2 * d.n1 - 1 - 2 * x1;
@@ -704,7 +716,7 @@ __device__ __forceinline__ void gather_x1wall(const void *src, const InstDesc &d
 // crossings n_c = floor(y / L), every crossing reverses the velocity.
 // Returns the source storage column x2*n3p + x3 within the source row
 // (written to row).
-template <int C1, int C2, int C3>
+template <int C1, int C2, int C3, bool OPEN2 = true>
 __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, int x2, int x3, bool &flip,
                                                     int &row)
 {
@@ -720,7 +732,7 @@ __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, i
             int s1 = x1 - C1;
             s1 = s1 < 0 ? 0 : (s1 > d.n1 - 1 ? d.n1 - 1 : s1);
             row = s1;
-            return wrap_axis(x2 - C2, d.n2) * d.n3p + wrap_axis(x3 - C3, d.n3);
+            return axis2(x2 - C2, d.n2, OPEN2 && (d.walls & 16)) * d.n3p + wrap_axis(x3 - C3, d.n3);
         }
         int back = 1 << 28, front = 1 << 28;
         if constexpr (C1 != 0) {
@@ -751,7 +763,7 @@ __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, i
         }
         int s1 = x1 - h1 * sb, s2 = x2 - h2 * sb, s3 = x3 - h3 * sb;
         if (!(d.walls & 1)) s1 = wrap_axis(s1, d.n1);
-        s2 = wrap_axis(s2, d.n2);
+        s2 = axis2(s2, d.n2, OPEN2 && (d.walls & 16));
         if (!(d.walls & 4)) s3 = wrap_axis(s3, d.n3);
         row = s1;
         return s2 * d.n3p + s3;
@@ -759,7 +771,7 @@ __host__ __device__ __forceinline__ int fold_source(const InstDesc &d, int x1, i
 }
 
 // General pull (any lane position, walls on any axis).
-template <int ST, class R>
+template <int ST, bool OPEN2 = true, class R>
 __device__ __forceinline__ void gather_general(const void *src, const InstDesc &d, int x1, int x2, int x3,
                                                const R &ref, typename Codec<ST>::G (&g)[Q])
 {
@@ -770,7 +782,7 @@ __device__ __forceinline__ void gather_general(const void *src, const InstDesc &
         constexpr int qo = opposite(q);
         bool flip;
         int row;
-        const int col = fold_source<CV[q][0], CV[q][1], CV[q][2]>(d, x1, x2, x3, flip, row);
+        const int col = fold_source<CV[q][0], CV[q][1], CV[q][2], OPEN2>(d, x1, x2, x3, flip, row);
         const uint32_t qs = flip ? (uint32_t)qo : (uint32_t)q;
         const uint32_t e = ((uint32_t)row * (uint32_t)Q + qs) * (uint32_t)d.Pp + (uint32_t)col;
         C r = C(0);

@@ -36,6 +36,9 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
 {
     using T = typename Codec<ST>::T;
     using C = typename Codec<ST>::C;
+    // open theta ends are served by the general-pattern kernels only (a batch
+    // with an open instance runs them); the others compile the periodic wrap
+    constexpr bool OPEN2 = PAT == PAT_GEN;
     __shared__ double red[8][3];
 
     const int ntiles = load_uniform(a.ntiles);
@@ -90,21 +93,21 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
         if (valid) {
             typename Codec<ST>::G g[Q];
             if (!wall1_row && !any3 && (d.walls & 4)) {
-                gather_fast_walled3<ST, EQW>(src, d, x1, x2, x3, R, g);
+                gather_fast_walled3<ST, EQW, OPEN2>(src, d, x1, x2, x3, R, g);
             } else if (!wall1_row && !any3) {
                 LaneOffsets L;
-                L.init(x2, x3, d.n2, d.n3, d.n3p, true, S);
+                L.init(x2, x3, d.n2, d.n3, d.n3p, true, OPEN2 && (d.walls & 16), S);
                 gather_fast<ST, EQW>(src, d, x1, L, R, g);
             } else if (!wall1_row && d.n3 >= 5) {
                 LaneOffsets L;
-                L.init(x2, x3, d.n2, d.n3, d.n3p, false, S);
-                gather_x3wall<ST>(src, d, x1, x2, x3, L, R, g);
+                L.init(x2, x3, d.n2, d.n3, d.n3p, false, OPEN2 && (d.walls & 16), S);
+                gather_x3wall<ST, OPEN2>(src, d, x1, x2, x3, L, R, g);
             } else if (!any3) {
                 LaneOffsets L;
-                L.init(x2, x3, d.n2, d.n3, d.n3p, !(d.walls & 4), S);
-                gather_x1wall<ST>(src, d, x1, x2, x3, L, R, g);
+                L.init(x2, x3, d.n2, d.n3, d.n3p, !(d.walls & 4), OPEN2 && (d.walls & 16), S);
+                gather_x1wall<ST, OPEN2>(src, d, x1, x2, x3, L, R, g);
             } else {
-                gather_general<ST>(src, d, x1, x2, x3, R, g);
+                gather_general<ST, OPEN2>(src, d, x1, x2, x3, R, g);
             }
             // per cross-section geometry; only the general pattern may depend on theta
             const int gidx = PAT == PAT_GEN ? geo_index(d, x1, x2, x3) : x1 * d.n3g + (d.n3g > 1 ? x3 : 0);

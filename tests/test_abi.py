@@ -66,6 +66,22 @@ def test_kernel_streaming_fold_with_equilibrium_walls_equals_oracle(n1, n2, n3):
     assert np.array_equal(src * 41 + sq, pm)
 
 
+@pytest.mark.parametrize("n1,n2,n3,walls", [
+    (n1, n2, n3, w) for n1, n2, n3, w in itertools.product([4, 7], [4, 5, 9], [1, 4, 6], [16, 17, 20, 21, 1 | 8 | 16])
+    if not ((w & 4) and n3 < 4)
+])
+def test_kernel_streaming_fold_with_open_theta_equals_oracle(n1, n2, n3, walls):
+    """Open theta ends (the inlet and outlet of Sec. IV): a pull from beyond
+    an end slab reads that slab, alone and together with every wall; the
+    kernels' fold and the oracle's pull map agree, and every source lies in
+    the domain."""
+    case = K.Case(kind="flat", n1=n1, n2=n2, n3=n3, walls=walls, width=1.0)
+    src, sq = mlbm.pull_map(case)
+    assert src.min() >= 0 and src.max() < case.N
+    pm = O.Sim(case).pull_map()
+    assert np.array_equal(src * 41 + sq, pm)
+
+
 def test_kernel_streaming_fold_at_benchmark_sizes():
     for case in (K.laminar_cylinder(), K.cylinder_sweep(De_values=[40.0])[0], K.ellipsoid_96x192_cases()[0]):
         src, sq = mlbm.pull_map(case)
@@ -76,7 +92,7 @@ def test_kernel_streaming_fold_at_benchmark_sizes():
 
 @pytest.mark.parametrize("bad", [
     dict(n1=0), dict(tau=0.5), dict(tau=0.3), dict(width=0.0), dict(walls=8), dict(walls=1 | 4 | 8),
-    dict(walls=16),
+    dict(walls=32), dict(walls=1 | 16, n2=3),
     dict(n1=3), dict(check_every=3), dict(precision="f64", forcing_mode=2),
     dict(kind="ellipsoid", b=0.0), dict(kind="ellipsoid", n3=4000, b=1.0),
     # largest sizes: a population buffer of 4 GiB or more, and a cross

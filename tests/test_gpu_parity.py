@@ -62,6 +62,14 @@ TINY = [
     ("cyl-eq-old", K.cylinder_case(0.8, 9, 2, 6, 0.8, De=10.0, forcing_mode=1, eq_walls=True)),
     ("ell-eq", K.ellipsoid_case(20.0, 5.0, 12, 2, 16, 0.6, De=5.0, eq_walls=True)),
     ("cyl-eq-wide", K.cylinder_case(0.9, 10, 2, 140, 0.75, De=10.0, eq_walls=True)),
+    # open theta ends (the inlet and outlet of Sec. IV): alone, with x1 walls,
+    # with both walls through every gather, and with equilibrium walls
+    ("flat-open", K.Case(kind="flat", n1=5, n2=6, n3=7, walls=K.WALL_OPEN2, width=1.0, tau=0.8, force=2e-3)),
+    ("cyl-open", K.cylinder_case(0.9, 8, 6, 8, 0.8, De=10.0).replace(walls=K.WALL_AXIS1 | K.WALL_OPEN2)),
+    ("cyl-w13-open-wide", K.cylinder_case(0.9, 10, 5, 140, 0.75, De=10.0, walls3=True).replace(
+        walls=K.WALL_AXIS1 | K.WALL_AXIS3 | K.WALL_OPEN2)),
+    ("flat-eq-open", K.Case(kind="flat", n1=6, n2=5, n3=5, walls=K.WALL_AXIS1 | K.WALL_EQ | K.WALL_OPEN2, width=1.0,
+                            tau=0.7, force=2e-3)),
 ]
 
 
@@ -636,6 +644,12 @@ FULL_CASES = [
                         tau=0.8, force=1e-3)),
     ("full-eq", K.Case(kind="ellipsoid_full", n1=9, n2=30, n3=8, walls=K.WALL_AXIS1 | K.WALL_EQ, r_inner=2.5,
                        width=1.0, b=1.3, tau=0.85, force=1e-3)),
+    # the open theta sector of Sec. IV (inlet and outlet)
+    ("full-open", K.Case(kind="ellipsoid_full", n1=8, n2=24, n3=8, walls=K.WALL_AXIS1 | K.WALL_OPEN2, r_inner=3.0,
+                         width=1.0, b=1.2, tau=0.8, force=1e-3)),
+    ("full-open-eq", K.Case(kind="ellipsoid_full", n1=9, n2=20, n3=8,
+                            walls=K.WALL_AXIS1 | K.WALL_EQ | K.WALL_OPEN2, r_inner=2.5, width=1.0, b=0.9,
+                            tau=0.85, force=1e-3)),
 ]
 
 

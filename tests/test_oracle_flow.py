@@ -438,3 +438,49 @@ def test_ellipsoid_mean_velocity_weights():
     assert abs(vm - 1.0) < 1e-14
     nu = (case.tau - 0.5) * O.lib().orc_cs2() * case.dt
     assert abs(De - case.width / nu * math.sqrt(case.width / (case.r_inner * case.b ** 2))) < 1e-9
+
+
+@pytest.mark.parametrize("make", [
+    lambda walls: K.cylinder_case(0.9, 8, 5, 6, 0.8, De=10.0).replace(walls=walls),
+    lambda walls: K.ellipsoid_case(40.0, 20.0, 8, 6, 10, 0.7, De=8.0).replace(walls=walls),
+])
+def test_open_theta_ends_keep_a_theta_invariant_flow(make):
+    """Open theta ends (the inlet and outlet of Sec. IV, read as zero-gradient
+    in-flow): on a geometry whose metric does not depend on theta, a flow
+    that is the same in every theta slab is advanced exactly as with periodic
+    theta, since every clamped source holds the value its periodic image
+    holds."""
+    per = make(K.WALL_AXIS1)
+    opn = make(K.WALL_AXIS1 | K.WALL_OPEN2)
+    init = K.perturbed_start(per, seed=4, amp=0.05)
+    a, b = O.Sim(per, init_u=init), O.Sim(opn, init_u=init)
+    a.step(300)
+    b.step(300)
+    assert np.array_equal(a.get_f(), b.get_f())
+
+
+def test_open_theta_outlet_disturbance_does_not_wrap_to_the_inlet():
+    """Brute force on a tiny grid: flat periodic box with open theta ends at
+    rest (f = w), the populations of the outlet slab x2 = n2 - 1 disturbed
+    (no walls, so every source is x - c). One step later every node whose 41 sources (x - c with the
+    theta index clamped into the domain) avoid that slab is still exactly at
+    rest, in particular the inlet slab x2 = 0; with periodic theta the inlet
+    side receives the disturbance."""
+    c, w, _, _ = O.lattice()
+    for walls, open_ in ((K.WALL_OPEN2, True), (0, False)):
+        case = K.Case(kind="flat", n1=6, n2=9, n3=4, walls=walls, width=1.0, tau=0.8)
+        S = O.Sim(case)
+        f = np.broadcast_to(w[:, None, None, None], (41, 6, 9, 4)).copy()
+        rng = np.random.default_rng(3)
+        f[:, :, 8, :] *= 1.0 + 0.01 * rng.random((41, 6, 4))
+        S.set_f(f)
+        S.step(1)
+        g = S.get_f()
+        for x2 in range(9):
+            touched = any(min(max(x2 - c[q, 1], 0), 8) == 8 if open_ else (x2 - c[q, 1]) % 9 == 8
+                          for q in range(41))
+            at_rest = np.array_equal(g[:, :, x2, :], np.broadcast_to(w[:, None, None], (41, 6, 4)))
+            if not touched:
+                assert at_rest, (open_, x2)
+        inlet_rest = np.array_equal(g[:, :, 0, :], np.broadcast_to(w[:, None, None], (41, 6, 4)))
+        assert inlet_rest == open_
