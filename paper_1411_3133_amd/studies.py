@@ -103,10 +103,14 @@ def _onsets(rows, key, reading="De_measured", ks=(2, 4, 6)):
 
 
 def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=None, tol=1e-8,
-                          max_steps=600_000, precision="f64", seed=1411, log=None):
+                          max_steps=600_000, precision="f64", seed=1411, log=None, geometry="slab"):
     """Sec. IV A ("b": values are R_theta = b^2 at r_i = 1) or Sec. IV B ("ri":
     values are R_phi = r_i at R_theta = 1), all curvatures and De of one
-    study in one batch run to a steady state."""
+    study in one batch run to a steady state. geometry "slab": the
+    streamwise-periodic slab with the metric frozen at theta = 0 (four theta
+    slabs); "full": the full metric of Sec. IV at every node over L_theta =
+    64 slabs of the Sec. IV B spacing, with open theta ends (inlet and
+    outlet)."""
     if values is None:
         values = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2, 1.4) if which == "b" else \
                  (0.8, 0.9, 1.0, 1.1, 1.2, 1.4, 1.55, 1.8)
@@ -119,9 +123,13 @@ def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=N
         for De in De_grid:
             # 64 radial spacings: 64 fluid rows between halfway walls, or 65
             # rows of which the first and last are the wall nodes
-            cases.append(K.ellipsoid_case(9.0 * R_th, 9.0 * R_ph, 65 if eq else 64, 4, 128, 1.0, De=De,
-                                          precision=precision, eq_walls=eq,
-                                          label=f"ell-{which}{v:g}-{walls}-De{De:g}"))
+            c = K.ellipsoid_case(9.0 * R_th, 9.0 * R_ph, 65 if eq else 64, 4, 128, 1.0, De=De,
+                                 precision=precision, eq_walls=eq, label=f"ell-{which}{v:g}-{walls}-De{De:g}")
+            if geometry == "full":
+                c = c.replace(kind="ellipsoid_full", n2=64, walls=c.walls | K.WALL_OPEN2,
+                              label=c.label.replace("ell-", "full-"))
+                c.force = K.nominal_force(c, De)
+            cases.append(c)
             meta.append((v, R_th, R_ph))
     inits = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
     t0 = time.perf_counter()
@@ -134,8 +142,10 @@ def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=N
         rows.append({"value": v, "R_theta": R_th, "R_phi": R_ph, "De_nominal": c.target_De, "De_measured": De_m,
                      "omega": om, "cells": W.cell_count(c, u), "steps": int(steps[i]), "status": int(status[i])})
     b.close()
-    out = {"study": which, "walls": walls, "precision": precision, "tol": tol, "max_steps": max_steps, "tau": 1.0,
-           "grid": "64 x 4 x 128 spacings (r, theta slab, phi)", "seconds": round(time.perf_counter() - t0, 1),
+    grid = "64 x 4 x 128 spacings (r, theta slab, phi)" if geometry == "slab" else \
+        "64 x 64 x 128 spacings (r, theta with open ends, phi), full metric"
+    out = {"study": which, "geometry": geometry, "walls": walls, "precision": precision, "tol": tol,
+           "max_steps": max_steps, "tau": 1.0, "grid": grid, "seconds": round(time.perf_counter() - t0, 1),
            "runs": rows, "onsets": {}}
     for v in values:
         out["onsets"][f"{v:g}"] = _onsets([r for r in rows if r["value"] == v], v)
@@ -149,6 +159,8 @@ def main():
                     help="default: bounce-back for eta, equilibrium (the paper's) for ellipsoid")
     ap.add_argument("--etas", default="0.8,0.85,0.9,0.95")
     ap.add_argument("--sweep", choices=["b", "ri"], default="b")
+    ap.add_argument("--geometry", choices=["slab", "full"], default="slab")
+    ap.add_argument("--De", default=None, help="comma-separated nominal De values")
     ap.add_argument("--values", default=None, help="comma-separated R_theta (b) or R_phi (ri) values")
     ap.add_argument("--max-steps", type=int, default=None)
     ap.add_argument("--tol", type=float, default=None)
@@ -161,8 +173,10 @@ def main():
                                        max_steps=args.max_steps or 1_000_000, precision=args.precision, log=log)
     else:
         values = None if args.values is None else tuple(float(x) for x in args.values.split(","))
-        res = paper_ellipsoid_sweep(args.sweep, values, args.walls or "equilibrium", tol=args.tol or 1e-8,
-                                    max_steps=args.max_steps or 600_000, precision=args.precision, log=log)
+        De_grid = None if args.De is None else [float(x) for x in args.De.split(",")]
+        res = paper_ellipsoid_sweep(args.sweep, values, args.walls or "equilibrium", De_grid=De_grid,
+                                    tol=args.tol or 1e-8, max_steps=args.max_steps or 600_000,
+                                    precision=args.precision, log=log, geometry=args.geometry)
     print(json.dumps(res), flush=True)
 
 

@@ -90,3 +90,17 @@ def test_eta_study_builds_the_paper_channel(fake_steady):
     for eta in ("0.8", "0.9"):
         lo, hi = r["onsets"][eta]["De_measured"]["k2"]
         assert lo < 0.95 * ONSET <= hi
+
+
+def test_ellipsoid_study_full_geometry_has_open_theta_ends(fake_steady):
+    """The full-geometry variant: the metric of Sec. IV at every node over 64
+    theta slabs, open at both ends, the same curvatures and force."""
+    r = studies.paper_ellipsoid_sweep("b", (0.8, 1.2), "equilibrium", De_grid=[20.0, 30.0], geometry="full")
+    (cases,) = fake_steady
+    slab = studies.paper_ellipsoid_sweep("b", (0.8, 1.2), "equilibrium", De_grid=[20.0, 30.0])
+    for c, cs in zip(cases, fake_steady[1]):
+        assert c.kind == "ellipsoid_full" and c.n2 == 64 and (c.walls & K.WALL_OPEN2)
+        assert (c.r_inner, c.b, c.n1, c.n3, c.tau) == (cs.r_inner, cs.b, cs.n1, cs.n3, cs.tau)
+        assert c.force == pytest.approx(K.nominal_force(c, c.target_De))
+    assert r["geometry"] == "full" and slab["geometry"] == "slab"
+
