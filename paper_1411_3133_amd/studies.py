@@ -22,8 +22,10 @@ theta = 0 (four theta slabs), so the open theta ends of Sec. IV are not
 modelled. It reports the knee of <omega> against the measured De and the
 2-, 4- and 6-cell onsets by cell count per curvature.
 
-Run as `python -m paper_1411_3133_amd.studies eta --walls bounce|equilibrium`
-or `python -m paper_1411_3133_amd.studies ellipsoid --sweep b|ri` (one
+Run as `python -m paper_1411_3133_amd.studies eta --walls bounce|equilibrium`,
+`python -m paper_1411_3133_amd.studies resolution` (the channel at eta = 0.9
+on three grids) or `python -m paper_1411_3133_amd.studies ellipsoid --sweep
+b|ri [--geometry full]` (one
 MI355X); each prints one JSON document. Orchestration only: every step runs
 in libmlbm's kernels.
 """
@@ -86,6 +88,37 @@ def paper_cylinder_eta_sweep(etas=(0.8, 0.85, 0.9, 0.95), walls="bounce", De_gri
                 res[reading][f"k{k}"] = None if first is None else [
                     rs[first - 1][reading] if first > 0 else None, rs[first][reading]]
         out["onsets"][f"{eta:g}"] = res
+    return out
+
+
+def paper_cylinder_resolution(eta=0.9, Lrs=(32, 64, 128), walls="bounce", De_grid=None, tol=1e-9,
+                              max_steps=1_000_000, precision="f64", seed=1411, log=None):
+    """Sec. III's resolution check (its Fig. 6 studies the error of De_c
+    against the grid at eta = 0.9): the validation channel at L_r = 32, 64,
+    128 radial spacings (L_z = 2 L_r, tau = 0.9), every resolution and De in
+    one batch; the knee of <omega> and the 2-cell bracket per resolution."""
+    if De_grid is None:
+        De_grid = [float(d) for d in range(30, 51)]
+    eq = walls == "equilibrium"
+    cases, lr_of = [], []
+    for Lr in Lrs:
+        for De in De_grid:
+            cases.append(K.cylinder_case(eta, Lr + 1 if eq else Lr, 1, 2 * Lr, 0.9, De=De, precision=precision,
+                                         eq_walls=eq, label=f"res{Lr}-{walls}-De{De:g}"))
+            lr_of.append(Lr)
+    inits = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
+    t0 = time.perf_counter()
+    b, steps, status, secs = W.run_to_steady(cases, inits, tol, max_steps, chunk=50000, log=log)
+    rows = []
+    for i, c in enumerate(cases):
+        om, vm, De_m = b[i].vortex_intensity()
+        _, u = b[i].moments()
+        rows.append({"value": lr_of[i], "De_nominal": c.target_De, "De_measured": De_m, "omega": om,
+                     "cells": W.cell_count(c, u), "steps": int(steps[i]), "status": int(status[i])})
+    b.close()
+    out = {"study": "resolution", "eta": eta, "walls": walls, "precision": precision, "tol": tol,
+           "max_steps": max_steps, "tau": 0.9, "seconds": round(time.perf_counter() - t0, 1), "runs": rows,
+           "onsets": {str(Lr): _onsets([r for r in rows if r["value"] == Lr], Lr, ks=(2, 4)) for Lr in Lrs}}
     return out
 
 
@@ -154,7 +187,7 @@ def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=N
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["eta", "ellipsoid"])
+    ap.add_argument("study", choices=["eta", "ellipsoid", "resolution"])
     ap.add_argument("--walls", choices=["bounce", "equilibrium"], default=None,
                     help="default: bounce-back for eta, equilibrium (the paper's) for ellipsoid")
     ap.add_argument("--etas", default="0.8,0.85,0.9,0.95")
@@ -167,7 +200,10 @@ def main():
     ap.add_argument("--precision", default="f64")
     args = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)
-    if args.study == "eta":
+    if args.study == "resolution":
+        res = paper_cylinder_resolution(walls=args.walls or "bounce", tol=args.tol or 1e-9,
+                                        max_steps=args.max_steps or 1_000_000, precision=args.precision, log=log)
+    elif args.study == "eta":
         etas = tuple(float(x) for x in args.etas.split(","))
         res = paper_cylinder_eta_sweep(etas, args.walls or "bounce", tol=args.tol or 1e-9,
                                        max_steps=args.max_steps or 1_000_000, precision=args.precision, log=log)

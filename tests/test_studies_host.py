@@ -104,3 +104,13 @@ def test_ellipsoid_study_full_geometry_has_open_theta_ends(fake_steady):
         assert c.force == pytest.approx(K.nominal_force(c, c.target_De))
     assert r["geometry"] == "full" and slab["geometry"] == "slab"
 
+
+def test_resolution_study_builds_three_grids(fake_steady):
+    r = studies.paper_cylinder_resolution(Lrs=(32, 64), De_grid=[28.0, 30.0, 32.0, 34.0, 36.0])
+    (cases,) = fake_steady
+    assert [(c.n1, c.n3) for c in cases[:1] + cases[-1:]] == [(32, 64), (64, 128)]
+    assert all(c.kind == "cylinder" and c.tau == 0.9 and c.n2 == 1 for c in cases)
+    for Lr in ("32", "64"):
+        lo, hi = r["onsets"][Lr]["k2"]
+        assert lo < 0.95 * ONSET <= hi
+
