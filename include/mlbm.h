@@ -182,6 +182,18 @@ mlbm_status mlbm_moments(mlbm_handle h, double *rho, double *u, int on_device);
  * Waits for the stream. */
 mlbm_status mlbm_vortex_intensity(mlbm_handle h, double *omega_mean, double *v_mean, double *De);
 
+/* The same observables restricted to the theta slabs x2_begin <= x2 <
+ * x2_end: every sum above runs over the nodes of those slabs only (the area
+ * too), so a one-slab range gives the cross-section averages of Sec. IV at
+ * that theta.  On the full ellipsoid the slab x2 sits at theta = (x2 + 1/2
+ * - n2/2) dtheta, so theta = 0 lies between slabs n2/2 - 1 and n2/2 (pass
+ * [n2/2 - 1, n2/2 + 1) for the pair around it).  [0, n2) gives
+ * mlbm_vortex_intensity's values bit for bit.  Output pointers may be NULL.
+ * Waits for the stream.  Errors: E_ARG (null handle; an empty range or one
+ * outside [0, n2)), E_HIP. */
+mlbm_status mlbm_vortex_intensity_slabs(mlbm_handle h, int x2_begin, int x2_end, double *omega_mean,
+                                        double *v_mean, double *De);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the same observables as
  * mlbm_vortex_intensity, bit for bit, computed with no device or host

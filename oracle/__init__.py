@@ -68,6 +68,8 @@ def lib():
                                   C.POINTER(C.c_double)]
     L.orc_observables_u.argtypes = [C.c_void_p, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double)]
+    L.orc_observables_slabs.argtypes = [C.c_void_p, _dp, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
     L.orc_check.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
     L.orc_check.restype = C.c_double
     L.orc_run_until.argtypes = [C.c_void_p, C.c_double, C.c_long, C.c_long,
@@ -206,12 +208,26 @@ class Sim:
         lib().orc_observables(self._h, C.byref(om), C.byref(v), C.byref(de))
         return om.value, v.value, de.value
 
-    def observables_u(self, u):
-        """(<omega>, <v_theta>, De) of a given physical velocity field [3][n1][n2][n3]."""
+    def observables_u(self, u, slabs=None):
+        """(<omega>, <v_theta>, De) of a given physical velocity field
+        [3][n1][n2][n3], over every theta slab or over slabs = (x2_begin, x2_end)."""
         om, v, de = C.c_double(), C.c_double(), C.c_double()
-        lib().orc_observables_u(self._h, np.ascontiguousarray(u, np.float64).reshape(-1),
-                                C.byref(om), C.byref(v), C.byref(de))
+        uu = np.ascontiguousarray(u, np.float64).reshape(-1)
+        if uu.size != 3 * self.N:
+            raise ValueError(f"velocity field of {uu.size} values, expected {3 * self.N}")
+        if slabs is None:
+            lib().orc_observables_u(self._h, uu, C.byref(om), C.byref(v), C.byref(de))
+        else:
+            lo, hi = int(slabs[0]), int(slabs[1])
+            if not 0 <= lo < hi <= self.shape[1]:
+                raise ValueError(f"slab range [{lo}, {hi}) is empty or outside [0, {self.shape[1]})")
+            lib().orc_observables_slabs(self._h, uu, lo, hi, C.byref(om), C.byref(v), C.byref(de))
         return om.value, v.value, de.value
+
+    def observables_slabs(self, x2_begin, x2_end):
+        """(<omega>, <v_theta>, De) of the current state over the theta slabs
+        x2_begin <= x2 < x2_end."""
+        return self.observables_u(self.moments()[1], slabs=(x2_begin, x2_end))
 
     def check(self):
         bad = C.c_int()

@@ -747,20 +747,22 @@ static double ddx(const double *v, int n1, int n3, int axis, int walled, int x1,
  *              S = int r dr dphi; flat: unweighted mean of |d_3 u^1 - d_1 u^3|.
  *   De = <v_theta> d / nu * sqrt(d / R), nu = (tau - 1/2) cs2 Dt,
  *        R = r_i (cylinder), R_theta = r_i b^2 (ellipsoid); 0 for flat space.
- * Averages over the theta slabs.  With equilibrium walls the integrals over
- * r run over the wall nodes with the trapezoidal rule (half weight at r_i
- * and r_o). */
-void orc_observables_u(const orc_sim *S, const double *u, double *omega_mean, double *v_mean,
-                       double *De)
+ * Averages over the theta slabs x2_begin <= x2 < x2_end (every integral,
+ * the area S too, is a sum over the nodes of those slabs: one slab gives the
+ * cross-section averages of Sec. IV at that theta).  With equilibrium walls
+ * the integrals over r run over the wall nodes with the trapezoidal rule
+ * (half weight at r_i and r_o). */
+void orc_observables_slabs(const orc_sim *S, const double *u, int x2_begin, int x2_end, double *omega_mean,
+                           double *v_mean, double *De)
 {
     const orc_case *c = &S->cs;
     const long N = S->N;
-    const int n1 = c->n1, n2 = c->n2, n3 = c->n3;
+    const int n1 = c->n1, n3 = c->n3;
     const double h1 = S->dt * S->s[0], h3 = S->dt * S->s[2];
     double *ur = (double *)malloc(sizeof(double) * n1 * n3);
     double *uz = (double *)malloc(sizeof(double) * n1 * n3);
     double om_num = 0.0, v_num = 0.0, area = 0.0;
-    for (int x2 = 0; x2 < n2; ++x2) {
+    for (int x2 = x2_begin; x2 < x2_end; ++x2) {
         for (int x1 = 0; x1 < n1; ++x1)
             for (int x3 = 0; x3 < n3; ++x3) {
                 long n = node_index(c, x1, x2, x3);
@@ -794,6 +796,12 @@ void orc_observables_u(const orc_sim *S, const double *u, double *omega_mean, do
         *De = (*v_mean) * c->width / nu * sqrt(c->width / R);
     }
     free(ur); free(uz);
+}
+
+/* The averages over every theta slab. */
+void orc_observables_u(const orc_sim *S, const double *u, double *omega_mean, double *v_mean, double *De)
+{
+    orc_observables_slabs(S, u, 0, S->cs.n2, omega_mean, v_mean, De);
 }
 
 void orc_observables(const orc_sim *S, double *omega_mean, double *v_mean, double *De)

@@ -1107,10 +1107,13 @@ mlbm_status mlbm_moments(mlbm_handle h, double *rho, double *u, int on_device)
     return MLBM_OK;
 }
 
-mlbm_status mlbm_vortex_intensity(mlbm_handle h, double *omega_mean, double *v_mean, double *De)
+// Observables over the theta slabs [x2lo, x2hi): moments into the batch
+// scratch, per-block partial sums on the device, the block sums in block
+// order on the host.
+static mlbm_status vortex_over_slabs(mlbm_handle h, int x2lo, int x2hi, double *omega_mean, double *v_mean,
+                                     double *De)
 {
     Instance *I = inst_of(h);
-    if (!I) return fail(MLBM_E_ARG, "null handle");
     Batch *B = h->b;
     const size_t N = (size_t)I->hd.N;
     const int nb = (int)((N + 255) / 256);
@@ -1120,7 +1123,8 @@ mlbm_status mlbm_vortex_intensity(mlbm_handle h, double *omega_mean, double *v_m
     HIP_TRY(launch_moments(B->d_insts + h->idx, I->hd, B->st, parity_of(*I), nullptr, du, B->stream));
     int nblocks = 0;
     const mlbm_desc &d = I->desc;
-    HIP_TRY(launch_vortex(I->hd, d.kind, d.b, I->dt * I->hd.s[0], I->dt * I->hd.s[2], du, dpart, &nblocks, B->stream));
+    HIP_TRY(launch_vortex(I->hd, d.kind, d.b, I->dt * I->hd.s[0], I->dt * I->hd.s[2], x2lo, x2hi, du, dpart,
+                          &nblocks, B->stream));
     std::vector<double> part(3 * (size_t)nblocks);
     HIP_TRY(hipMemcpyAsync(part.data(), dpart, sizeof(double) * part.size(), hipMemcpyDeviceToHost, B->stream));
     HIP_TRY(hipStreamSynchronize(B->stream));
@@ -1128,6 +1132,25 @@ mlbm_status mlbm_vortex_intensity(mlbm_handle h, double *omega_mean, double *v_m
     for (int k = 0; k < nblocks; ++k) { vs += part[3 * k]; os += part[3 * k + 1]; as += part[3 * k + 2]; }
     observables_from_sums(*I, vs, os, as, omega_mean, v_mean, De);
     return MLBM_OK;
+}
+
+mlbm_status mlbm_vortex_intensity(mlbm_handle h, double *omega_mean, double *v_mean, double *De)
+{
+    Instance *I = inst_of(h);
+    if (!I) return fail(MLBM_E_ARG, "null handle");
+    return vortex_over_slabs(h, 0, I->desc.n2, omega_mean, v_mean, De);
+}
+
+mlbm_status mlbm_vortex_intensity_slabs(mlbm_handle h, int x2_begin, int x2_end, double *omega_mean,
+                                        double *v_mean, double *De)
+{
+    Instance *I = inst_of(h);
+    if (!I) return fail(MLBM_E_ARG, "null handle");
+    if (x2_begin < 0 || x2_end > I->desc.n2 || x2_begin >= x2_end)
+        return fail(MLBM_E_ARG, "mlbm_vortex_intensity_slabs: slab range [" + std::to_string(x2_begin) + ", " +
+                                    std::to_string(x2_end) + ") is empty or outside [0, " +
+                                    std::to_string(I->desc.n2) + ")");
+    return vortex_over_slabs(h, x2_begin, x2_end, omega_mean, v_mean, De);
 }
 
 mlbm_status mlbm_vortex_intensity_noalloc(mlbm_handle h, double *omega_mean, double *v_mean, double *De)
@@ -1151,7 +1174,8 @@ mlbm_status mlbm_vortex_intensity_noalloc(mlbm_handle h, double *omega_mean, dou
     HIP_TRY(launch_moments(B->d_insts + h->idx, I->hd, B->st, parity_of(*I), nullptr, du, B->stream));
     int nblocks = 0;
     const mlbm_desc &d = I->desc;
-    HIP_TRY(launch_vortex(I->hd, d.kind, d.b, I->dt * I->hd.s[0], I->dt * I->hd.s[2], du, dpart, &nblocks, B->stream));
+    HIP_TRY(launch_vortex(I->hd, d.kind, d.b, I->dt * I->hd.s[0], I->dt * I->hd.s[2], 0, d.n2, du, dpart,
+                          &nblocks, B->stream));
     HIP_TRY(launch_sum_partials(dpart, nblocks, dsum, B->stream));
     double sums[3] = {0.0, 0.0, 0.0};
     HIP_TRY(hipMemcpyAsync(sums, dsum, sizeof(sums), hipMemcpyDeviceToHost, B->stream));

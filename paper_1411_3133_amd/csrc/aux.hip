@@ -396,14 +396,15 @@ __device__ __forceinline__ double ddx_axis(const double *f, int stride, int x, i
     return (f[(xp - x) * stride] - f[(xm - x) * stride]) / (2.0 * h);
 }
 
-__global__ void vortex_kernel(InstDesc d, int kind, double b, double h1, double h3, const double *u,
-                              double *partials)
+__global__ void vortex_kernel(InstDesc d, int kind, double b, double h1, double h3, int x2lo, int x2hi,
+                              const double *u, double *partials)
 {
     __shared__ double red[4][3];
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
     double vs = 0.0, os = 0.0, as = 0.0;
-    if (n < d.N) {
-        const int x1 = n / d.P, col = n - x1 * d.P, x2 = col / d.n3, x3 = col - x2 * d.n3;
+    // nodes of the theta slabs [x2lo, x2hi) contribute; the rest add zeros
+    if (n < d.N && x2 >= x2lo && x2 < x2hi) {
         const int NX = geo_stride(d);
         const int gi = geo_index(d, x1, x2, x3);
         const double r = d.geo[G_X1 * NX + gi], ph = d.geo[G_X3 * NX + gi];
@@ -438,12 +439,12 @@ __global__ void vortex_kernel(InstDesc d, int kind, double b, double h1, double 
     }
 }
 
-hipError_t launch_vortex(const InstDesc &h, int kind, double b, double h1, double h3, const double *u,
-                         double *partials, int *nblocks, hipStream_t s)
+hipError_t launch_vortex(const InstDesc &h, int kind, double b, double h1, double h3, int x2lo, int x2hi,
+                         const double *u, double *partials, int *nblocks, hipStream_t s)
 {
     const int nb = (h.N + 255) / 256;
     *nblocks = nb;
-    hipLaunchKernelGGL(vortex_kernel, dim3(nb), dim3(256), 0, s, h, kind, b, h1, h3, u, partials);
+    hipLaunchKernelGGL(vortex_kernel, dim3(nb), dim3(256), 0, s, h, kind, b, h1, h3, x2lo, x2hi, u, partials);
     return hipGetLastError();
 }
 

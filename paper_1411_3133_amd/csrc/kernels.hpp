@@ -50,8 +50,9 @@ hipError_t launch_moments(const InstDesc *d_desc, const InstDesc &h_desc, int st
                           double *rho, double *u, hipStream_t s);
 
 // observables: partial sums [blocks][3] of (v numerator, omega numerator, area)
-hipError_t launch_vortex(const InstDesc &h_desc, int kind, double b, double h1, double h3, const double *u,
-                         double *partials, int *nblocks, hipStream_t s);
+// over the nodes of the theta slabs x2lo <= x2 < x2hi
+hipError_t launch_vortex(const InstDesc &h_desc, int kind, double b, double h1, double h3, int x2lo, int x2hi,
+                         const double *u, double *partials, int *nblocks, hipStream_t s);
 // out[0..2] = sums of the partial triples over blocks 0..nb-1, in block order
 hipError_t launch_sum_partials(const double *partials, int nb, double *out, hipStream_t s);
 

@@ -44,7 +44,7 @@ class Desc(C.Structure):
 
 EXPORTS = [
     "mlbm_init_geometry", "mlbm_step", "mlbm_moments", "mlbm_vortex_intensity",
-    "mlbm_vortex_intensity_noalloc", "mlbm_residual",
+    "mlbm_vortex_intensity_noalloc", "mlbm_vortex_intensity_slabs", "mlbm_residual",
     "mlbm_run_until", "mlbm_get_populations", "mlbm_set_populations", "mlbm_step_nodes",
     "mlbm_time", "mlbm_pull_map", "mlbm_save", "mlbm_load", "mlbm_destroy", "mlbm_last_error", "mlbm_lattice",
     "mlbm_batch_create", "mlbm_batch_step", "mlbm_batch_run_until", "mlbm_batch_get",
@@ -83,6 +83,7 @@ def load():
     L.mlbm_moments.argtypes = [vp, vp, vp, C.c_int]
     L.mlbm_vortex_intensity.argtypes = [vp, dp, dp, dp]
     L.mlbm_vortex_intensity_noalloc.argtypes = [vp, dp, dp, dp]
+    L.mlbm_vortex_intensity_slabs.argtypes = [vp, C.c_int, C.c_int, dp, dp, dp]
     L.mlbm_residual.argtypes = [vp, dp, C.POINTER(C.c_int)]
     L.mlbm_run_until.argtypes = [vp, C.c_double, i64, C.POINTER(i64)]
     L.mlbm_get_populations.argtypes = [vp, vp]
@@ -260,6 +261,13 @@ class Sim:
         """(<omega>, <v_theta>, De)."""
         om, v, de = C.c_double(), C.c_double(), C.c_double()
         _check(load().mlbm_vortex_intensity(self._h, C.byref(om), C.byref(v), C.byref(de)))
+        return om.value, v.value, de.value
+
+    def vortex_intensity_slabs(self, x2_begin: int, x2_end: int):
+        """(<omega>, <v_theta>, De) over the theta slabs x2_begin <= x2 < x2_end."""
+        om, v, de = C.c_double(), C.c_double(), C.c_double()
+        _check(load().mlbm_vortex_intensity_slabs(self._h, int(x2_begin), int(x2_end), C.byref(om), C.byref(v),
+                                                  C.byref(de)))
         return om.value, v.value, de.value
 
     def vortex_intensity_noalloc(self):

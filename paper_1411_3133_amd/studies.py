@@ -79,14 +79,15 @@ def paper_cylinder_eta_sweep(etas=(0.8, 0.85, 0.9, 0.95), walls="bounce", De_gri
     for eta in etas:
         rs = sorted([r for r in rows if abs(r["eta"] - eta) < 1e-9], key=lambda r: r["De_nominal"])
         ok = [r for r in rs if r["status"] == 0]
+        stable = [r for r in rs if r["status"] in (0, 1)]       # brackets as in _onsets
         res = {}
         for reading in ("De_measured", "De_angular"):
             res[reading] = {"knee": sweep.knee([r[reading] for r in ok], [r["omega"] for r in ok])
                             if len(ok) >= 4 else None}
             for k in (2, 4):
-                first = next((j for j, r in enumerate(rs) if r["cells"] >= k), None)
+                first = next((j for j, r in enumerate(stable) if r["cells"] >= k), None)
                 res[reading][f"k{k}"] = None if first is None else [
-                    rs[first - 1][reading] if first > 0 else None, rs[first][reading]]
+                    stable[first - 1][reading] if first > 0 else None, stable[first][reading]]
         out["onsets"][f"{eta:g}"] = res
     return out
 
@@ -124,14 +125,17 @@ def paper_cylinder_resolution(eta=0.9, Lrs=(32, 64, 128), walls="bounce", De_gri
 
 def _onsets(rows, key, reading="De_measured", ks=(2, 4, 6)):
     """Knee of <omega> over the converged runs and cell-count brackets
-    (last run below, first at or above k cells) of one curve."""
+    (last run below, first at or above k cells) of one curve over the runs
+    that stayed stable: a run stopped by the step cap still shows its cells
+    (slow settling is expected next to an onset), an unstable one has none."""
     rs = sorted(rows, key=lambda r: r["De_nominal"])
     ok = [r for r in rs if r["status"] == 0]
+    stable = [r for r in rs if r["status"] in (0, 1)]
     res = {"knee": sweep.knee([r[reading] for r in ok], [r["omega"] for r in ok]) if len(ok) >= 4 else None}
     for k in ks:
-        first = next((j for j, r in enumerate(rs) if r["cells"] >= k), None)
-        res[f"k{k}"] = None if first is None else [rs[first - 1][reading] if first > 0 else None,
-                                                   rs[first][reading]]
+        first = next((j for j, r in enumerate(stable) if r["cells"] >= k), None)
+        res[f"k{k}"] = None if first is None else [stable[first - 1][reading] if first > 0 else None,
+                                                   stable[first][reading]]
     return res
 
 
@@ -143,7 +147,8 @@ def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=N
     streamwise-periodic slab with the metric frozen at theta = 0 (four theta
     slabs); "full": the full metric of Sec. IV at every node over L_theta =
     64 slabs of the Sec. IV B spacing, with open theta ends (inlet and
-    outlet)."""
+    outlet), its observables and cell count read on the two slabs around
+    theta = 0."""
     if values is None:
         values = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2, 1.4) if which == "b" else \
                  (0.8, 0.9, 1.0, 1.1, 1.2, 1.4, 1.55, 1.8)
@@ -169,11 +174,22 @@ def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=N
     b, steps, status, secs = W.run_to_steady(cases, inits, tol, max_steps, chunk=50000, log=log)
     rows = []
     for i, c in enumerate(cases):
-        om, vm, De_m = b[i].vortex_intensity()
         _, u = b[i].moments()
         v, R_th, R_ph = meta[i]
-        rows.append({"value": v, "R_theta": R_th, "R_phi": R_ph, "De_nominal": c.target_De, "De_measured": De_m,
-                     "omega": om, "cells": W.cell_count(c, u), "steps": int(steps[i]), "status": int(status[i])})
+        row = {"value": v, "R_theta": R_th, "R_phi": R_ph, "De_nominal": c.target_De}
+        if geometry == "full":
+            # Sec. IV reads the cross-section at theta = 0: the two slabs
+            # around it; the averages over the whole sector are kept beside
+            lo, hi = c.n2 // 2 - 1, c.n2 // 2 + 1
+            om, vm, De_m = b[i].vortex_intensity_slabs(lo, hi)
+            om_all, _, De_all = b[i].vortex_intensity()
+            row.update(omega_all=om_all, De_all=De_all, cells_all=W.cell_count(c, u))
+            cells = W.cell_count(c, u[:, :, lo:hi])
+        else:
+            om, vm, De_m = b[i].vortex_intensity()
+            cells = W.cell_count(c, u)
+        row.update(De_measured=De_m, omega=om, cells=cells, steps=int(steps[i]), status=int(status[i]))
+        rows.append(row)
     b.close()
     grid = "64 x 4 x 128 spacings (r, theta slab, phi)" if geometry == "slab" else \
         "64 x 64 x 128 spacings (r, theta with open ends, phi), full metric"

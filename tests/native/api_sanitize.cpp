@@ -62,6 +62,10 @@ int main(int argc, char **argv)
         double om = 0, v = 0, De = 0, om2 = 0, v2 = 0, De2 = 0;
         EXPECT(mlbm_vortex_intensity(h, &om, &v, &De) == MLBM_OK && De > 0);
         EXPECT(mlbm_vortex_intensity_noalloc(h, &om2, &v2, &De2) == MLBM_OK && De2 == De && om2 == om);
+        EXPECT(mlbm_vortex_intensity_slabs(h, 0, 4, &om2, &v2, &De2) == MLBM_OK && De2 == De && om2 == om);
+        EXPECT(mlbm_vortex_intensity_slabs(h, 1, 2, &om2, nullptr, &De2) == MLBM_OK && std::isfinite(De2));
+        EXPECT(mlbm_vortex_intensity_slabs(h, 2, 2, &om2, &v2, &De2) == MLBM_E_ARG);
+        EXPECT(mlbm_vortex_intensity_slabs(h, 0, 5, &om2, &v2, &De2) == MLBM_E_ARG);
         EXPECT(mlbm_get_populations(h, f.data()) == MLBM_OK);
         EXPECT(mlbm_set_populations(h, f.data()) == MLBM_OK);
         const std::string ck = dir + "/api_sanitize.ckpt";

@@ -440,6 +440,56 @@ def test_ellipsoid_mean_velocity_weights():
     assert abs(De - case.width / nu * math.sqrt(case.width / (case.r_inner * case.b ** 2))) < 1e-9
 
 
+def test_one_slab_vorticity_of_a_z_wave_confined_to_that_slab():
+    """The z wave of the cylinder test placed in theta slab 1 of 3 only: over
+    that slab alone <omega> takes the closed form of the whole-channel wave,
+    over the other slabs it is zero, and over all three it is a third."""
+    case = K.cylinder_case(0.9, 8, 3, 16, 0.8, De=5.0)
+    S = O.Sim(case)
+    r, z = K.node_coords(case)
+    h = case.dt
+    k = 2 * math.pi / (case.n3 * h)
+    u = np.zeros((3, 8, 3, 16))
+    u[0, :, 1, :] = (1e-2 * np.sin(k * z))[None, :]
+    exp = 1e-2 * math.sin(k * h) / h * np.abs(np.cos(k * z)).mean() * r.mean()
+    om1, vm1, _ = S.observables_u(u, slabs=(1, 2))
+    assert abs(om1 - exp) < 1e-12 * exp and vm1 == 0.0
+    assert S.observables_u(u, slabs=(0, 1))[0] == 0.0
+    assert S.observables_u(u, slabs=(2, 3))[0] == 0.0
+    assert abs(S.observables_u(u)[0] - exp / 3) < 1e-12 * exp
+    assert S.observables_u(u, slabs=(0, 3)) == S.observables_u(u)
+
+
+def test_slab_observables_of_the_full_ellipsoid_partition_the_theta_sum():
+    """Every theta slab of the full ellipsoid has the same cross-section
+    (r and phi do not depend on theta), so the all-slab averages are the
+    means of the one-slab ones and a pair of slabs gives the mean of the two;
+    De is <v_theta> times one constant on every range."""
+    case = K.Case(kind="ellipsoid_full", n1=6, n2=8, n3=6, walls=K.WALL_AXIS1 | K.WALL_OPEN2, r_inner=10.0,
+                  width=1.0, b=1.5, tau=0.8, force=1e-5)
+    S = O.Sim(case)
+    u = np.random.default_rng(5).normal(size=(3, 6, 8, 6)) * 1e-2
+    u[1] += 0.05
+    one = np.array([S.observables_u(u, slabs=(k, k + 1)) for k in range(8)])
+    allv = np.array(S.observables_u(u))
+    assert np.all(np.abs(one.mean(axis=0) - allv) <= 1e-13 * np.abs(allv))
+    pair = np.array(S.observables_u(u, slabs=(3, 5)))
+    assert np.all(np.abs(one[3:5].mean(axis=0) - pair) <= 1e-13 * np.abs(pair))
+    ratio = one[:, 2] / one[:, 1]
+    assert np.all(np.abs(ratio / (allv[2] / allv[1]) - 1) < 1e-13)
+    # slabs really differ on this field, so the partition is not trivial
+    assert one[:, 0].std() > 1e-3 * one[:, 0].mean()
+
+
+@pytest.mark.parametrize("bad", [(0, 0), (3, 2), (-1, 2), (0, 9)])
+def test_slab_range_is_checked(bad):
+    case = K.Case(kind="ellipsoid_full", n1=6, n2=8, n3=6, walls=K.WALL_AXIS1 | K.WALL_OPEN2, r_inner=10.0,
+                  width=1.0, b=1.5, tau=0.8, force=1e-5)
+    S = O.Sim(case)
+    with pytest.raises(ValueError):
+        S.observables_u(np.zeros((3, 6, 8, 6)), slabs=bad)
+
+
 @pytest.mark.parametrize("make", [
     lambda walls: K.cylinder_case(0.9, 8, 5, 6, 0.8, De=10.0).replace(walls=walls),
     lambda walls: K.ellipsoid_case(40.0, 20.0, 8, 6, 10, 0.7, De=8.0).replace(walls=walls),

@@ -22,6 +22,11 @@ class _Inst:
         om = 1e-3 + 0.02 * max(0.0, De - 0.95 * ONSET)       # a knee at measured 0.95 ONSET
         return om, 1.0, De
 
+    def vortex_intensity_slabs(self, lo, hi):
+        om, v, De = self.vortex_intensity()
+        self.case.slab_calls.append((lo, hi))
+        return 2.0 * om, v, De                               # told apart from the all-slab value
+
     def moments(self):
         c = self.case
         u = np.zeros((3, c.n1, c.n2, c.n3))
@@ -37,6 +42,8 @@ class _Batch:
         self.cases = cases
 
     def __getitem__(self, i):
+        if not hasattr(self.cases[i], "slab_calls"):
+            object.__setattr__(self.cases[i], "slab_calls", [])
         return _Inst(self.cases[i])
 
     def close(self):
@@ -102,6 +109,10 @@ def test_ellipsoid_study_full_geometry_has_open_theta_ends(fake_steady):
         assert c.kind == "ellipsoid_full" and c.n2 == 64 and (c.walls & K.WALL_OPEN2)
         assert (c.r_inner, c.b, c.n1, c.n3, c.tau) == (cs.r_inner, cs.b, cs.n1, cs.n3, cs.tau)
         assert c.force == pytest.approx(K.nominal_force(c, c.target_De))
+        assert c.slab_calls == [(31, 33)]                    # the two slabs around theta = 0
+    for row in r["runs"]:
+        assert row["omega"] == pytest.approx(2.0 * row["omega_all"]) and row["cells"] == row["cells_all"]
+    assert all("omega_all" not in row for row in slab["runs"])
     assert r["geometry"] == "full" and slab["geometry"] == "slab"
 
 
@@ -114,3 +125,14 @@ def test_resolution_study_builds_three_grids(fake_steady):
         lo, hi = r["onsets"][Lr]["k2"]
         assert lo < 0.95 * ONSET <= hi
 
+
+
+def test_onset_brackets_skip_unstable_runs_and_keep_capped_ones():
+    """The knee reads converged runs only; a cell bracket skips a run that
+    went unstable (no state to read) but keeps one stopped by the step cap."""
+    def row(De, cells, status):
+        return {"De_nominal": De, "De_measured": De, "omega": 0.01 * De, "cells": cells, "status": status}
+    rows = [row(20.0, 0, 0), row(24.0, 0, 0), row(28.0, 6, 2), row(32.0, 2, 1), row(36.0, 2, 0), row(40.0, 4, 0)]
+    o = studies._onsets(rows, "x")
+    assert o["k2"] == [24.0, 32.0]          # the unstable run at 28 is not the onset
+    assert o["k4"] == [36.0, 40.0] and o["k6"] is None
