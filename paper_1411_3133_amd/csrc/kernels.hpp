@@ -14,6 +14,7 @@ struct StepArgs {
     double *partials;        // [tiles][3] check sums
     int parity;              // read f[parity], write f[parity ^ 1]
     int xcd_group = 0;       // 1: each XCD takes a contiguous eighth of the tile queue
+    int group_log2 = 0;      // else: runs of 2^group_log2 consecutive tiles per XCD, interleaved
 };
 
 hipError_t launch_step(const StepArgs &a, int pat, int st, bool check, bool eqw, int grid, int block, hipStream_t s);

@@ -46,12 +46,20 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
     // its own L2. Neighbouring tiles of a row share the cache lines that
     // their x3 pulls straddle; with xcd_group each XCD takes one contiguous
     // eighth of the queue instead of every eighth tile, so that a straddled
-    // line is fetched once, not by two XCDs. (A bijection of [0, ntiles);
-    // with a persistent grid that is a multiple of 8 it holds on every pass.)
+    // line is fetched once, not by two XCDs. Without it the queue is dealt
+    // to the XCDs in runs of G = 2^group_log2 consecutive tiles (G = 1:
+    // every eighth tile): the tiles of one run, neighbours in a row, share
+    // the straddled lines and the cross-section geometry in one L2 while
+    // all XCDs still stream through neighbouring memory; the last
+    // ntiles mod 8G tiles keep their order. (Both maps are bijections of
+    // [0, ntiles); with a persistent grid that is a multiple of 8 the
+    // grouping holds on every pass.)
     const int per = ntiles >> 3, rem = ntiles & 7;
+    const int lg = a.group_log2, full = ntiles & ~((8 << lg) - 1);
     for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
-        const int xcd = v & 7;
-        const int t = a.xcd_group ? xcd * per + min(xcd, rem) + (v >> 3) : v;
+        const int xcd = v & 7, s = v >> 3;
+        const int t = a.xcd_group ? xcd * per + min(xcd, rem) + s
+                                  : (v < full ? ((((s >> lg) << 3) + xcd) << lg) | (s & ((1 << lg) - 1)) : v);
         const Tile tl = load_uniform(a.tiles + t);
         const InstDesc d = load_uniform(a.insts + tl.inst);
         const int x1 = tl.x1;
