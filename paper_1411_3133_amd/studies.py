@@ -140,7 +140,8 @@ def _onsets(rows, key, reading="De_measured", ks=(2, 4, 6)):
 
 
 def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=None, tol=1e-8,
-                          max_steps=600_000, precision="f64", seed=1411, log=None, geometry="slab"):
+                          max_steps=600_000, precision="f64", seed=1411, log=None, geometry="slab",
+                          start="laminar"):
     """Sec. IV A ("b": values are R_theta = b^2 at r_i = 1) or Sec. IV B ("ri":
     values are R_phi = r_i at R_theta = 1), all curvatures and De of one
     study in one batch run to a steady state. geometry "slab": the
@@ -148,7 +149,9 @@ def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=N
     slabs); "full": the full metric of Sec. IV at every node over L_theta =
     64 slabs of the Sec. IV B spacing, with open theta ends (inlet and
     outlet), its observables and cell count read on the two slabs around
-    theta = 0."""
+    theta = 0. start: "laminar" (the closed-form profile of the slab) or
+    "rest" (the flow grows from rest under the body force), each plus the
+    seeded perturbation."""
     if values is None:
         values = (0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 1.1, 1.2, 1.4) if which == "b" else \
                  (0.8, 0.9, 1.0, 1.1, 1.2, 1.4, 1.55, 1.8)
@@ -169,7 +172,9 @@ def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=N
                 c.force = K.nominal_force(c, De)
             cases.append(c)
             meta.append((v, R_th, R_ph))
-    inits = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
+    base = {"laminar": "poiseuille", "rest": "rest"}[start]
+    inits = [K.perturbed_start(c, seed=seed + i, amp=1e-4, base=base, U_nom=K.nominal_velocity(c, c.target_De))
+             for i, c in enumerate(cases)]
     t0 = time.perf_counter()
     b, steps, status, secs = W.run_to_steady(cases, inits, tol, max_steps, chunk=50000, log=log)
     rows = []
@@ -193,7 +198,7 @@ def paper_ellipsoid_sweep(which="b", values=None, walls="equilibrium", De_grid=N
     b.close()
     grid = "64 x 4 x 128 spacings (r, theta slab, phi)" if geometry == "slab" else \
         "64 x 64 x 128 spacings (r, theta with open ends, phi), full metric"
-    out = {"study": which, "geometry": geometry, "walls": walls, "precision": precision, "tol": tol,
+    out = {"study": which, "geometry": geometry, "start": start, "walls": walls, "precision": precision, "tol": tol,
            "max_steps": max_steps, "tau": 1.0, "grid": grid, "seconds": round(time.perf_counter() - t0, 1),
            "runs": rows, "onsets": {}}
     for v in values:
@@ -214,6 +219,8 @@ def main():
     ap.add_argument("--max-steps", type=int, default=None)
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--precision", default="f64")
+    ap.add_argument("--start", choices=["laminar", "rest"], default="laminar",
+                    help="ellipsoid: closed-form laminar start or flow grown from rest")
     args = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)
     if args.study == "resolution":
@@ -228,7 +235,8 @@ def main():
         De_grid = None if args.De is None else [float(x) for x in args.De.split(",")]
         res = paper_ellipsoid_sweep(args.sweep, values, args.walls or "equilibrium", De_grid=De_grid,
                                     tol=args.tol or 1e-8, max_steps=args.max_steps or 600_000,
-                                    precision=args.precision, log=log, geometry=args.geometry)
+                                    precision=args.precision, log=log, geometry=args.geometry,
+                                    start=args.start)
     print(json.dumps(res), flush=True)
 
 

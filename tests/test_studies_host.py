@@ -11,6 +11,7 @@ from paper_1411_3133_amd import studies
 from paper_1411_3133_amd import warmstart as W
 
 ONSET = 31.0        # nominal De of the 2-cell onset in the fake runs
+seen_inits = []     # initial fields handed to the fake batched runs
 
 
 class _Inst:
@@ -53,9 +54,11 @@ class _Batch:
 @pytest.fixture
 def fake_steady(monkeypatch):
     seen = []
+    seen_inits.clear()
 
     def run_to_steady(cases, inits, tol, max_steps, **kw):
         seen.append(list(cases))
+        seen_inits.append(list(inits))
         n = len(cases)
         return _Batch(cases), np.full(n, 1000), np.zeros(n, np.int32), 0.01
 
@@ -136,3 +139,18 @@ def test_onset_brackets_skip_unstable_runs_and_keep_capped_ones():
     o = studies._onsets(rows, "x")
     assert o["k2"] == [24.0, 32.0]          # the unstable run at 28 is not the onset
     assert o["k4"] == [36.0, 40.0] and o["k6"] is None
+
+
+def test_full_geometry_rest_start(fake_steady):
+    """start="rest": the same cases begin from rest plus the seeded
+    perturbation (amplitude 1e-4 of the nominal speed), not from the
+    laminar profile."""
+    studies.paper_ellipsoid_sweep("b", (1.2,), "equilibrium", De_grid=[40.0], geometry="full", start="rest")
+    studies.paper_ellipsoid_sweep("b", (1.2,), "equilibrium", De_grid=[40.0], geometry="full")
+    (c,), (c2,) = fake_steady
+    (rest,), (lam,) = seen_inits
+    U = K.nominal_velocity(c, 40.0)
+    r, ph = K.node_coords(c)
+    speed = rest[1] * (r[:, None, None] * c.b * np.cos(ph)[None, None, :])   # physical streamwise speed
+    assert np.abs(speed).max() <= 1e-4 * U * (1 + 1e-12)
+    assert np.abs(lam[1] - rest[1]).max() > 0.1 * np.abs(lam[1]).max()
