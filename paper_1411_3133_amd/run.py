@@ -1,7 +1,8 @@
 """Run the cases of a JSON case file (`cases.cases_from_json`) to a steady
 state on one MI355X, in one batch, and log the run as JSON lines: after every
 chunk of steps one line per instance with its step count, window residual,
-<omega>, <v_theta> and De (Sec. III, Eq. (8)), status, precision, tau and
+<omega>, <v_theta> and De (Sec. III, Eq. (8); on the full ellipsoid also
+<omega> and De on the theta = 0 cross-section), status, precision, tau and
 seed, and the batch's rate over the chunk (MLUPS and the fraction of the
 8 TB/s HBM peak that its algorithmic bytes, 2 x 41 values per node and step,
 amount to over the chunk's wall-clock time, host work included); a last line
@@ -36,9 +37,14 @@ def run_case_file(text: str, tol: float, max_steps: int, chunk: int, out, precis
                 "hbm_frac": round(alg / secs / HBM_PEAK, 4) if secs > 0 else None}
         for i, c in enumerate(cases):
             om, v, De = b[i].vortex_intensity()
-            out.write(json.dumps({"label": c.label, "step": int(steps[i]), "residual": float(res[i]),
-                                  "omega": om, "v_theta": v, "De": De, "status": int(status[i]),
-                                  "precision": c.precision, "tau": c.tau, "seed": starts[i][0], **rate}) + "\n")
+            line = {"label": c.label, "step": int(steps[i]), "residual": float(res[i]),
+                    "omega": om, "v_theta": v, "De": De, "status": int(status[i]),
+                    "precision": c.precision, "tau": c.tau, "seed": starts[i][0], **rate}
+            if c.kind == "ellipsoid_full":
+                # Sec. IV's reading: the cross-section at theta = 0, between the middle slabs
+                om0, _, De0 = b[i].vortex_intensity_slabs(c.n2 // 2 - 1, c.n2 // 2 + 1)
+                line.update(omega_theta0=om0, De_theta0=De0)
+            out.write(json.dumps(line) + "\n")
         out.flush()
 
     b, steps, status, secs = W.run_to_steady(cases, inits, tol, max_steps, chunk=chunk, on_chunk=on_chunk)

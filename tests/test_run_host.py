@@ -49,6 +49,9 @@ class _Inst:
     def vortex_intensity(self):
         return 0.1 * self.i, 1.0 + self.i, 20.0 + self.i
 
+    def vortex_intensity_slabs(self, lo, hi):
+        return 100.0 + lo, 1.0, 200.0 + hi
+
 
 class _Batch:
     def __getitem__(self, i):
@@ -82,3 +85,24 @@ def test_run_logs_one_line_per_instance_and_chunk(monkeypatch):
     assert a["MLUPS"] == pytest.approx(nodes / 0.5 / 1e6, abs=0.1)
     assert a["hbm_frac"] == pytest.approx(2 * 41 * 4 * nodes / 0.5 / 8e12, abs=1e-4)
     assert a["precision"] == "f32" and a["tau"] == 0.8
+
+
+def test_full_ellipsoid_lines_carry_the_theta0_reading(monkeypatch):
+    """On the full ellipsoid each line adds <omega> and De over the two
+    slabs around theta = 0 (n2 = 24: slabs 11 and 12); other kinds do not."""
+    full = K.Case(kind="ellipsoid_full", n1=8, n2=24, n3=8, walls=1, r_inner=3.0, width=1.0, b=1.2, tau=0.8,
+                  force=1e-3, label="full")
+    text = K.cases_to_json([full, K.laminar_cylinder("f32")], [1, 2])
+
+    def fake(cases, inits, tol, max_steps, chunk=20000, on_chunk=None, **kw):
+        b = _Batch()
+        steps = np.array([100, 100]); status = np.array([0, 0], np.int32)
+        on_chunk(b, 100, steps, np.array([1e-7, 1e-7]), status, np.array([100, 100]), 0.1)
+        return b, steps, status, 0.1
+
+    monkeypatch.setattr(W, "run_to_steady", fake)
+    out = io.StringIO()
+    R.run_case_file(text, 1e-6, 1000, 100, out)
+    a, b = [json.loads(x) for x in out.getvalue().splitlines()][:2]
+    assert (a["omega_theta0"], a["De_theta0"]) == (111.0, 213.0)
+    assert "omega_theta0" not in b
