@@ -267,15 +267,18 @@ def beyond_cache_leg(precision, steps=500, warmup=100, block=0, grid=0):
             "health": health}
 
 
-def critical_dean_leg(tol=1e-7, grid_points=9):
+def critical_dean_leg(tol=1e-7, grid_points=9, stall="fallback"):
     """Critical Dean numbers (onset of 2, 4 and 6 cells) of the 8 curvature
     pairs of the batched sweep at N_r = 32, by batched bisection to 1 %
     brackets. Each pair runs at the larger of the Mach-rule tau and its
     measured stability floor, over De from 20 to 200 or to the De where its
     mean lattice speed reaches Mach 0.3 at that tau. Once from plain starts;
     once with every run (first round included) started from a network
-    trained on the plain sweep's converged first-round fields, falling back
-    to the plain start where a warm run's residual stalls. Reports both, their largest
+    trained on the plain sweep's converged first-round fields. stall="stop":
+    in both sweeps a run whose residual stops falling (no 20 % over 50k
+    steps) stops there and its cells are counted like those of a run at the
+    step cap; "fallback": plain runs go to the tolerance or the cap, and a
+    stalled warm run restarts from the plain start. Reports both, their largest
     relative difference (measured De, bracket midpoints), the fallbacks per
     round and how many bracket ends finished from the warm start."""
     from paper_1411_3133_amd import cases as K
@@ -289,17 +292,18 @@ def critical_dean_leg(tol=1e-7, grid_points=9):
     def grid(top):
         return sweep.even_grid(20.0, top, grid_points)
 
-    log("critical De: plain starts")
-    plain = sweep.critical_dean(pairs, grid, tol=tol, max_steps=400000, log=log)
+    log(f"critical De: plain starts (stall rule: {stall})")
+    stop = {"stall": "stop", "stall_chunks": 5, "chunk": 10000} if stall == "stop" else {}
+    plain = sweep.critical_dean(pairs, grid, tol=tol, max_steps=400000, log=log, **stop)
     t0 = time.perf_counter()
     net = sweep.train_on(plain["dataset"])
     t_train = time.perf_counter() - t0
     log("critical De: warm starts")
     # near onset the plain runs need 80k-400k steps to reach the tolerance, so
-    # a warm run gets the whole budget and falls back only when its residual
-    # stops falling (no 20 % over 50k steps)
+    # a warm run gets the whole budget and stops (or falls back) only when its
+    # residual stops falling (no 20 % over 50k steps)
     warm = sweep.critical_dean(pairs, grid, tol=tol, max_steps=400000, net=net, log=log, fallback_after=None,
-                               stall_chunks=5, chunk=10000)
+                               stall_chunks=5, chunk=10000, stall=stall)
 
     def mid(x):
         return None if None in x else 0.5 * (x[0] + x[1])
@@ -326,6 +330,9 @@ def critical_dean_leg(tol=1e-7, grid_points=9):
         "max_rel_diff": round(max(diffs), 5) if diffs else None,
         "within_1pct": f"{sum(d <= 0.01 for d in diffs)}/{len(diffs)}",
         "bracket_ends_finished_warm": warm_ends,
+        "stall_rule": stall,
+        "stalled_plain_warm": [sum(r["stalled"] for r in plain["rounds"]),
+                               sum(r["stalled"] for r in warm["rounds"])],
         "warm_fallbacks_per_round": [r["fallbacks"] for r in warm["rounds"]],
         "warm_instances_per_round": [r["instances"] for r in warm["rounds"]],
         "seconds_plain": plain["seconds"], "seconds_warm": warm["seconds"], "train_seconds": round(t_train, 2),
@@ -348,6 +355,10 @@ def main():
                     help="unseen cases in the time-to-steady leg (0 skips it)")
     ap.add_argument("--steady-train", type=int, default=500, help="training fields for the warm start")
     ap.add_argument("--critical", type=int, default=1, help="run the critical-De leg (0 skips it)")
+    ap.add_argument("--critical-stall", choices=["fallback", "stop"], default="fallback",
+                    help="critical-De leg: a stalled warm run restarts from the plain start while plain runs go "
+                         "to the cap (default), or a stalled run stops in both sweeps (faster, but a stalled "
+                         "state's cell count can be a transient)")
     ap.add_argument("--sweep", type=int, default=1, help="time the cylinder sweep as a side leg (0 skips it)")
     ap.add_argument("--beyond-cache", type=int, default=1,
                     help="time one instance larger than the last-level cache (0 skips it)")
@@ -434,7 +445,7 @@ def main():
     if args.steady > 0:
         line["time_to_steady"] = time_to_steady(args.steady_train, args.steady)
     if args.critical:
-        line["critical_dean"] = critical_dean_leg()
+        line["critical_dean"] = critical_dean_leg(stall=args.critical_stall)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cases[0], inits[0])
     print(json.dumps(line), flush=True)

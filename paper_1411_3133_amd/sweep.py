@@ -23,18 +23,23 @@ from . import warmstart as W
 from .mlbm import Net
 
 
-def _run(cases, inits_plain, tol, max_steps, net=None, fallback_after=None, log=None, stall_chunks=3, chunk=5000):
+def _run(cases, inits_plain, tol, max_steps, net=None, fallback_after=None, log=None, stall_chunks=3, chunk=5000,
+         stall="fallback"):
     """Fields, steps, status, observables (<omega>, <v_theta>, measured De),
     seconds and the indices of runs that fell back to the plain start, of a
-    batch of cases."""
+    batch of cases. stall: "fallback" (a stalled warm run restarts from the
+    plain start; plain runs go to tol or the cap) or "stop" (any stalled
+    run, plain or warm, stops and keeps its state, status 3)."""
     if net is None:
-        b, steps, status, secs = W.run_to_steady(cases, inits_plain, tol, max_steps, log=log)
+        kw = {"stall_chunks": stall_chunks, "chunk": chunk} if stall == "stop" else {}
+        b, steps, status, secs = W.run_to_steady(cases, inits_plain, tol, max_steps, log=log, **kw)
         fields = [b[i].moments() for i in range(len(cases))]
         obs = [b[i].vortex_intensity() for i in range(len(cases))]
         b.close()
         return fields, steps, status, obs, secs, []
     fields, steps, status, secs, _, redo, _, obs = W.warm_start_run(net, cases, inits_plain, tol, max_steps,
-                                                                    fallback_after, log, stall_chunks, chunk)
+                                                                    fallback_after, log, stall_chunks, chunk,
+                                                                    stall_fallback=stall == "fallback")
     return fields, steps, status, obs, secs, list(redo)
 
 
@@ -84,13 +89,15 @@ def knee(De: Sequence[float], omega: Sequence[float]):
 def critical_dean(pairs: Sequence[Tuple], De_grid, ks: Sequence[int] = (2, 4, 6), rel_width: float = 0.01,
                   tol: float = 1e-6, max_steps: int = 200000, seed: int = 7, net: Optional[Net] = None,
                   fallback_after: Optional[int] = 60000, log=None, stall_chunks: int = 3,
-                  chunk: int = 5000) -> Dict:
+                  chunk: int = 5000, stall: str = "fallback") -> Dict:
     """Bracket the onset De of k cells for every pair ((name, make) or
     (name, make, De_top)); De_grid is one sequence of De for every pair, or a
     callable De_top -> sequence. With `net` every run starts from its
     prediction (plain start as fallback where a warm run stalls: no 20 %
     fall of its residual over stall_chunks chunks of `chunk` steps, or not
-    converged after fallback_after steps; None: the whole budget). Returns
+    converged after fallback_after steps; None: the whole budget). With
+    stall="stop" a stalled run, plain or warm, instead stops and keeps its
+    state, its cells counted like those of a run at the step cap. Returns
     brackets of nominal and measured De per (pair, k), the onset read off
     each pair's <omega>(measured De) curve of converged runs (`knee`), the
     cell counts and <omega> seen, wall time, instance-steps and fallbacks
@@ -105,13 +112,13 @@ def critical_dean(pairs: Sequence[Tuple], De_grid, ks: Sequence[int] = (2, 4, 6)
         cases = [make(De) for (_, make, De) in items]
         plain = [K.perturbed_start(c, seed=seed + i, amp=1e-4) for i, c in enumerate(cases)]
         fields, steps, status, obs, secs, redo = _run(cases, plain, tol, max_steps, net, fallback_after, log,
-                                                      stall_chunks, chunk)
+                                                      stall_chunks, chunk, stall)
         for j, ((name, _, De), c, (_, u), st, ob) in enumerate(zip(items, cases, fields, status, obs)):
             seen[(name, De)] = (W.cell_count(c, u), float(ob[2]), int(st), float(ob[0]),
                                 net is not None and j not in redo)
         rounds.append({"instances": len(items), "seconds": round(secs, 3), "instance_steps": int(np.sum(steps)),
                        "converged": int(np.sum(status == 0)), "unstable": int(np.sum(status == 2)),
-                       "fallbacks": len(redo)})
+                       "stalled": int(np.sum(status == 3)), "fallbacks": len(redo)})
         return cases, fields, status
 
     pairs = [(p[0], p[1], p[2] if len(p) > 2 else None) for p in pairs]

@@ -127,13 +127,15 @@ def cell_count(case: K.Case, u: np.ndarray, threshold: float = 0.1, floor: float
 
 def warm_start_run(net: Net, cases: Sequence[K.Case], plain_inits, tol: float, max_steps: int,
                    fallback_after: Optional[int] = None, log=None, stall_chunks: Optional[int] = 3,
-                   chunk: int = 5000):
+                   chunk: int = 5000, stall_fallback: bool = True):
     """Batched run from the network's prediction. An instance whose residual
     stalls (no 20 % fall below its best over stall_chunks chunks of `chunk`
     steps) or that has not reached tol after fallback_after steps is run
     again from its plain start (the fallback) with the full max_steps, in a
     second batch; its step count and the wall time include the abandoned
-    warm phase. Returns (fields, steps, status, seconds, inference_seconds,
+    warm phase. With stall_fallback=False a stalled instance keeps the state
+    it stalled in (status 3), as a plain run stopped by the same rule
+    would. Returns (fields, steps, status, seconds, inference_seconds,
     fallback_indices, warm_init, observables): fields[i] = (rho, u),
     observables[i] = (<omega>, <v_theta>, De) of the final state."""
     t0 = time.perf_counter()
@@ -144,7 +146,8 @@ def warm_start_run(net: Net, cases: Sequence[K.Case], plain_inits, tol: float, m
     fields = [bw[i].moments() for i in range(len(cases))]
     obs = [bw[i].vortex_intensity() for i in range(len(cases))]
     bw.close()
-    redo = [i for i in range(len(cases)) if stw[i] == 3 or (stw[i] != 0 and budget < max_steps)]
+    redo = [i for i in range(len(cases))
+            if (stw[i] == 3 and stall_fallback) or (stw[i] not in (0, 3) and budget < max_steps)]
     if redo:
         if log:
             log(f"  fallback to the plain start for {len(redo)} case(s)")

@@ -25,7 +25,8 @@ def _field(case, cells):
 def fake_runs(monkeypatch):
     calls = []
 
-    def fake_run(cases, inits, tol, max_steps, net=None, fallback_after=None, log=None, stall_chunks=3, chunk=5000):
+    def fake_run(cases, inits, tol, max_steps, net=None, fallback_after=None, log=None, stall_chunks=3, chunk=5000,
+                 stall="fallback"):
         calls.append(len(cases))
         fields, obs = [], []
         for c in cases:
