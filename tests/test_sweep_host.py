@@ -21,13 +21,18 @@ def _field(case, cells):
     return u
 
 
+rules = []          # stall rule handed to each batched run
+
+
 @pytest.fixture
 def fake_runs(monkeypatch):
     calls = []
+    rules.clear()
 
     def fake_run(cases, inits, tol, max_steps, net=None, fallback_after=None, log=None, stall_chunks=3, chunk=5000,
                  stall="fallback"):
         calls.append(len(cases))
+        rules.append(stall)
         fields, obs = [], []
         for c in cases:
             th = THRESH[c.label]
@@ -110,3 +115,14 @@ def test_per_pair_grids_warm_accounting_and_dataset(fake_runs):
     assert sum(1 for v in r["finished_warm"].values() if not v) == len(r["rounds"])
     assert len(r["dataset"]) == 10
     assert sweep.even_grid(20.0, 60.0, 5) == [20.0, 30.0, 40.0, 50.0, 60.0]
+
+
+def test_stall_rule_reaches_every_round(fake_runs):
+    """critical_dean(stall="stop") hands the rule to every batched run (plain
+    sweeps too), and each round reports its stalled runs."""
+    pairs = [("A", lambda De: K.ellipsoid_case(20.0, 30.0, 8, 2, 40, 0.6, De=De, label="A"))]
+    r = sweep.critical_dean(pairs, [20.0, 30.0, 40.0, 50.0], ks=(2,), rel_width=0.01, stall="stop")
+    assert len(rules) == len(r["rounds"]) > 1 and set(rules) == {"stop"}
+    assert all(rd["stalled"] == 0 for rd in r["rounds"])
+    sweep.critical_dean(pairs, [20.0, 30.0, 40.0, 50.0], ks=(2,), rel_width=0.01)
+    assert rules[-1] == "fallback"
