@@ -155,6 +155,34 @@ def time_to_steady(n_train, n_test, tol=1e-6, cap=150000):
     }
 
 
+def training_leg(iterations, warmup, batch=4096):
+    """The warm-start network's training kernels alone (forward, backward,
+    weight gradient, Adam), for profiling: a 5-64-64-64-3 network on the
+    nodes of 40 small ellipsoid slabs (24x4x48, perturbed laminar fields as
+    targets), `warmup` untimed then `iterations` timed Adam steps of
+    `batch` nodes. FLOPs per step: about 6 x parameters x batch."""
+    import torch
+    from paper_1411_3133_amd import cases as K
+    from paper_1411_3133_amd import mlbm
+    from paper_1411_3133_amd import warmstart as W
+
+    cs = K.warmstart_cases(40, seed=1)
+    net = mlbm.Net(64, 3, K.net_init_params(64, 3, seed=3))
+    for i, c in enumerate(cs):
+        De, R1, R2, U = W.case_params(c)
+        net.dataset_add(c, K.perturbed_start(c, seed=i, amp=0.05), De, R1, R2, U)
+    net.train(max(warmup, 1), batch=batch, lr=1e-3, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = net.train(iterations, batch=batch, lr=1e-3, seed=2)
+    wall = time.perf_counter() - t0
+    nparams = len(K.net_init_params(64, 3, seed=3))
+    return {"workload": f"warm-start network 5-64-64-64-3 (SiLU, FP32), {net.dataset_size} training nodes, "
+                        f"Adam steps of {batch} nodes",
+            "iterations": iterations, "ms_per_iteration": round(wall * 1e3 / iterations, 4),
+            "approx_TFLOPs": round(6 * nparams * batch * iterations / wall / 1e12, 4), "loss": float(loss)}
+
+
 def timed_batch(cases, inits, steps, warmup, block=0, grid=0):
     """Run `cases` as one batch on torch's current stream: autotuned (or the
     given) launch, `warmup` untimed steps rounded up to whole check windows
@@ -362,9 +390,10 @@ def main():
     ap.add_argument("--sweep", type=int, default=1, help="time the cylinder sweep as a side leg (0 skips it)")
     ap.add_argument("--beyond-cache", type=int, default=1,
                     help="time one instance larger than the last-level cache (0 skips it)")
-    ap.add_argument("--only", choices=["sweep", "beyond"], default=None,
-                    help="time only the cylinder sweep or the beyond-cache instance and print its leg "
-                         "(for profiling one kernel on one workload)")
+    ap.add_argument("--only", choices=["sweep", "beyond", "training"], default=None,
+                    help="time only the cylinder sweep, the beyond-cache instance or the warm-start "
+                         "network's training (--steps Adam steps) and print its leg (for profiling one "
+                         "kernel on one workload)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -391,6 +420,9 @@ def main():
         return
     if args.only == "beyond":
         print(json.dumps(beyond_cache_leg(args.precision, args.steps, args.warmup, args.block, args.grid)))
+        return
+    if args.only == "training":
+        print(json.dumps(training_leg(args.steps, args.warmup)))
         return
     cases, inits, wall, ev_ms, launch, health = uneven_batch_headline(
         args.precision, args.steps, args.warmup, args.block, args.grid)

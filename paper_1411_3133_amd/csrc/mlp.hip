@@ -29,7 +29,7 @@
 
 namespace {
 
-constexpr int NIN = 5, NOUT = 3, MAXDEPTH = 6, CHUNK = 256;
+constexpr int NIN = 5, NOUT = 3, MAXDEPTH = 6, CHUNK = 64;
 
 thread_local std::string g_net_err;
 
@@ -113,8 +113,11 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z)
 // Forward pass, one thread per sample, parameters staged in LDS (every lane
 // reads the same weight: broadcast, no bank conflicts).  If `hid` is given
 // the hidden pre-activations are kept for backpropagation ([n][depth][H]).
+// The launch bound (the CHUNK-thread blocks it always runs with) lets the
+// compiler keep a sample's activations in registers: without it the default
+// 1024-thread bound caps a lane at 128 VGPRs and the arrays spill to scratch.
 template <int H>
-__global__ void forward_kernel(const float *p, Shape sh, const float *X, int64_t M, uint64_t seed, int64_t n,
+__global__ __launch_bounds__(CHUNK) void forward_kernel(const float *p, Shape sh, const float *X, int64_t M, uint64_t seed, int64_t n,
                                float *Y, float *hid, int64_t *sel)
 {
     extern __shared__ float sp[];
@@ -161,7 +164,7 @@ __global__ void forward_kernel(const float *p, Shape sh, const float *X, int64_t
 // layer's pre-activations, dl [n][depth + 1][H] (the output layer uses the
 // first 3 entries of its slot), and per-chunk loss partial sums.
 template <int H>
-__global__ void backward_kernel(const float *p, Shape sh, const float *T, const int64_t *sel, int64_t n,
+__global__ __launch_bounds__(CHUNK) void backward_kernel(const float *p, Shape sh, const float *T, const int64_t *sel, int64_t n,
                                 const float *Y, const float *hid, float *dl, double *lossp)
 {
     extern __shared__ float sp[];
