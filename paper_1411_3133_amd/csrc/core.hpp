@@ -96,16 +96,32 @@ struct NodeGeo {
             return (C)gload<double>(geo, 8ull * e);
     }
 
-    __device__ __forceinline__ void load(const double *__restrict__ geo, const float *__restrict__ geof, int idx,
-                                         int stride, C force)
+    // On the double-curved slab (metric frozen at theta = 0) half of the
+    // fields depend on r alone: Delta^11, Delta^33, Gamma^1_33, Gamma^2_12
+    // and Gamma^3_13 take the same value at every node of an x1 row. They
+    // are read at the row's first node (ridx, the same address for every
+    // lane: one request per wavefront), the others at the node's own (idx).
+    static constexpr bool row_only(int f)
     {
+        return PAT == PAT_ELL &&
+               (f == G_D11 || f == G_D33 || f == G_1_33 || f == G_2_12 || f == G_3_13);
+    }
+
+    __device__ __forceinline__ void load(const double *__restrict__ geo, const float *__restrict__ geof, int idx,
+                                         int stride, C force, int ridx = -1)
+    {
+        if (ridx < 0) ridx = idx;
         static_for<0, 3>([&](auto I) {
             static_for<0, 3>([&](auto J) {
-                if constexpr (Mask<PAT>::D(I, J))
-                    D[I][J] = field(geo, geof, d_field(I, J), idx, stride);
+                if constexpr (Mask<PAT>::D(I, J)) {
+                    constexpr int f = d_field(I, J);
+                    D[I][J] = field(geo, geof, f, row_only(f) ? ridx : idx, stride);
+                }
                 static_for<0, 3>([&](auto K) {
-                    if constexpr (Mask<PAT>::G(I, J < K ? J : K, J < K ? K : J))
-                        Gm[I][J][K] = field(geo, geof, g_field(I, J, K), idx, stride);
+                    if constexpr (Mask<PAT>::G(I, J < K ? J : K, J < K ? K : J)) {
+                        constexpr int f = g_field(I, J, K);
+                        Gm[I][J][K] = field(geo, geof, f, row_only(f) ? ridx : idx, stride);
+                    }
                 });
             });
             if constexpr (Mask<PAT>::F(I))

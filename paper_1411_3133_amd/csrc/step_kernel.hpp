@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(512) step_kernel(StepArgs a)
             const int gidx = PAT == PAT_GEN ? geo_index(d, x1, x2, x3) : x1 * d.n3g + (d.n3g > 1 ? x3 : 0);
             const int gstride = PAT == PAT_GEN ? geo_stride(d) : d.n1 * d.n3g;
             NodeGeo<PAT, C> geo;
-            geo.load(d.geo, d.geof, gidx, gstride, (C)d.force);
+            geo.load(d.geo, d.geof, gidx, gstride, (C)d.force, PAT == PAT_GEN ? gidx : x1 * d.n3g);
             C rho, u[3];
             if (eq_row) {
                 wall_equilibrium<PAT, C, typename Codec<ST>::G, Codec<ST>::SCALED>(g, geo, rho);
